@@ -1,0 +1,183 @@
+"""FP64 CPU oracle of the ideal-MHD cell update (TEST INFRASTRUCTURE ONLY).
+
+This package wraps ``mhd_oracle.c``, a plain, slow, step-by-step C implementation
+of the Godunov finite-volume MHD cycle of Lesur et al. (arXiv:2304.13746,
+Sec. 2.2-2.7).  Only the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it; the GPU library never does, and
+the two share no code.
+
+States are dicts of eight float64 arrays shaped (nz, ny, nx): the cell-centred
+conserved variables ``rho, mx, my, mz, en`` and the face-centred field ``bx`` (at
+i-1/2), ``by`` (at j-1/2), ``bz`` (at k-1/2).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mhd_oracle.c")
+LIB = os.path.join(HERE, "libmhd_oracle.so")
+FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
+
+HLLD, HLL = 0, 1
+RK2, EULER = 0, 1
+OK, ERR_INVALID_ARG, ERR_NOMEM, ERR_NONPHYSICAL = 0, -1, -2, -4
+
+# -ffp-contract=off: no fused multiply-add, every expression rounds as written.
+CFLAGS = ["-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+          "-std=c11", "-Wall"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/libmhd_oracle.so``."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+                ("gamma", C.c_double), ("cfl", C.c_double),
+                ("riemann", C.c_int), ("integrator", C.c_int)]
+
+
+class _State(C.Structure):
+    _fields_ = [(f, C.POINTER(C.c_double)) for f in FIELDS]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.environ.get("MHD_ORACLE_LIB")  # alternative build (e.g. a planted mistake)
+        if not path:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build()
+            path = LIB
+        L = C.CDLL(path)
+        dp = C.POINTER(C.c_double)
+        L.orc_max_invdt.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp]
+        L.orc_step.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, C.c_int, C.c_double]
+        L.orc_diagnostics.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp]
+        L.orc_vanleer.argtypes = [C.c_double, C.c_double]
+        L.orc_vanleer.restype = C.c_double
+        for fn in (L.orc_fast_speed, L.orc_slow_speed):
+            fn.argtypes = [C.c_double] * 6
+            fn.restype = C.c_double
+        L.orc_riemann.argtypes = [C.c_int, C.c_double, C.c_int, dp, dp, dp, dp, dp]
+        L.orc_phys_flux.argtypes = [C.c_double, dp, C.c_double, dp, dp]
+        L.orc_corner_emf.argtypes = [C.c_double] * 12
+        L.orc_corner_emf.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Params:
+    nx: int
+    ny: int
+    nz: int
+    lx: float = 1.0
+    ly: float = 1.0
+    lz: float = 1.0
+    gamma: float = 5.0 / 3.0
+    cfl: float = 0.3
+    riemann: int = HLLD
+    integrator: int = RK2
+
+    def c(self) -> _Params:
+        return _Params(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.gamma,
+                       self.cfl, self.riemann, self.integrator)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _cstate(p: Params, s: dict) -> _State:
+    shape = (p.nz, p.ny, p.nx)
+    for f in FIELDS:
+        a = s[f]
+        if a.dtype != np.float64 or a.shape != shape or not a.flags.c_contiguous:
+            raise ValueError(f"field {f}: need C-contiguous float64 {shape}, got {a.dtype} {a.shape}")
+    return _State(*[_dptr(s[f]) for f in FIELDS])
+
+
+def copy_state(s: dict) -> dict:
+    return {f: np.array(s[f], dtype=np.float64, order="C", copy=True) for f in FIELDS}
+
+
+def max_invdt(p: Params, s: dict) -> float:
+    out = C.c_double(0.0)
+    rc = lib().orc_max_invdt(C.byref(p.c()), C.byref(_cstate(p, s)), C.byref(out))
+    if rc not in (OK,):
+        raise RuntimeError(f"orc_max_invdt failed: {rc}")
+    return out.value
+
+
+def step(p: Params, s: dict, t: float, dt_next: float, nsteps: int, t_stop: float = 0.0,
+         check: bool = True):
+    """Advance ``s`` in place by ``nsteps`` cycles; returns (t, dt_next, rc)."""
+    tt = C.c_double(t)
+    dd = C.c_double(dt_next)
+    rc = lib().orc_step(C.byref(p.c()), C.byref(_cstate(p, s)), C.byref(tt), C.byref(dd),
+                        int(nsteps), float(t_stop))
+    if check and rc != OK:
+        raise RuntimeError(f"orc_step failed: {rc}")
+    return tt.value, dd.value, rc
+
+
+def diagnostics(p: Params, s: dict) -> dict:
+    out = np.zeros(10)
+    rc = lib().orc_diagnostics(C.byref(p.c()), C.byref(_cstate(p, s)), _dptr(out))
+    if rc != OK:
+        raise RuntimeError(f"orc_diagnostics failed: {rc}")
+    return {"mass": out[0], "mom": out[1:4].copy(), "energy": out[4], "bflux": out[5:8].copy(),
+            "divb_max": out[8], "divb_rms": out[9]}
+
+
+def vanleer(dm: float, dp: float) -> float:
+    return lib().orc_vanleer(dm, dp)
+
+
+def fast_speed(gamma, rho, p, bn, bt1, bt2) -> float:
+    return lib().orc_fast_speed(gamma, rho, p, bn, bt1, bt2)
+
+
+def slow_speed(gamma, rho, p, bn, bt1, bt2) -> float:
+    return lib().orc_slow_speed(gamma, rho, p, bn, bt1, bt2)
+
+
+def riemann(solver: int, gamma: float, wl: np.ndarray, wr: np.ndarray, bn: np.ndarray):
+    """Face-frame Riemann fluxes for n faces: wl, wr (n, 7), bn (n,)."""
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    bn = np.ascontiguousarray(bn, dtype=np.float64)
+    n = bn.shape[0]
+    assert wl.shape == (n, 7) and wr.shape == (n, 7)
+    flux = np.zeros((n, 7))
+    cmax = np.zeros(n)
+    lib().orc_riemann(solver, gamma, n, _dptr(wl), _dptr(wr), _dptr(bn), _dptr(flux), _dptr(cmax))
+    return flux, cmax
+
+
+def phys_flux(gamma: float, w, bn: float):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    u = np.zeros(7)
+    f = np.zeros(7)
+    lib().orc_phys_flux(gamma, _dptr(w), bn, _dptr(u), _dptr(f))
+    return u, f
+
+
+def corner_emf(a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3) -> float:
+    return lib().orc_corner_emf(a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3)

@@ -1,0 +1,716 @@
+/*
+ * mhd_oracle.c -- plain FP64 CPU reference of one Godunov ideal-MHD cycle
+ * (Lesur et al., arXiv:2304.13746).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg to check the GPU library, never by the product.
+ * It shares no code with the GPU path.  Build: gcc -O2 -fopenmp -fno-fast-math
+ * -ffp-contract=off (no fused multiply-add, so every expression below rounds
+ * exactly as written, left to right).
+ *
+ * What is computed, in the paper's order (Sec. 2.2-2.7):
+ *   S1  conserved -> primitive variables; cell-centred B is the mean of the two
+ *       faces (the face-to-cell rule of Sec. 3.3 output).
+ *   S2  piecewise-linear reconstruction of (rho, v, B_t, p) with the van Leer
+ *       limiter (Sec. 2.3); B_n on a face is the staggered face value (Sec. 2.4).
+ *   S3  HLL (Einfeldt et al. 1991) or HLLD (Miyoshi & Kusano 2005) flux on every
+ *       x, y, z face; pressure is inside the momentum flux (Sec. 2.3).  The same
+ *       solve yields c_max for the CFL condition (eq. cfl).
+ *   S5  conservative update of (rho, m, E) by the flux divergence (eq. gal).
+ *   S7  corner EMFs with the upwind-by-contact scheme E^c of Gardiner & Stone
+ *       (2005), the default of Sec. 2.4.
+ *   S8  face-B update by the discrete Stokes theorem (constrained transport,
+ *       eq. ind_short).
+ *   Stages are combined as U_s = w_s U* + w0_s U_0 (Sec. 2.7, Tab. weights);
+ *   dt = sigma_CFL / max_V sum_d c_max,d / dl_d (eq. cfl) with eta = 0.
+ *
+ * Readings where the paper is silent (each one is also listed in the design
+ * notes): van Leer in harmonic form; wave-speed bounds S_L,R = min/max(v_n) -/+
+ * max(c_f) for both solvers; HLLD degenerate star states keep the tangential
+ * fields; sign(0) = 0 in the double-star states; the E^c upwind switch is the
+ * sign of the Riemann mass flux (0 -> average); dt is measured during the first
+ * stage of a cycle and used for the next one, the first dt by a pre-pass.
+ */
+#include "mhd_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ grid */
+
+typedef struct {
+  int nx, ny, nz;
+  long n;
+  double gamma, gm1, igm1;
+  double idl[3]; /* 1 / dl_d */
+  double dv;     /* cell volume */
+  int riemann;
+} grid_t;
+
+static void grid_init(grid_t* g, const orc_params* p) {
+  g->nx = p->nx;
+  g->ny = p->ny;
+  g->nz = p->nz;
+  g->n = (long)p->nx * p->ny * p->nz;
+  g->gamma = p->gamma;
+  g->gm1 = p->gamma - 1.0;
+  g->igm1 = 1.0 / g->gm1;
+  double dx = p->lx / p->nx, dy = p->ly / p->ny, dz = p->lz / p->nz;
+  g->idl[0] = 1.0 / dx;
+  g->idl[1] = 1.0 / dy;
+  g->idl[2] = 1.0 / dz;
+  g->dv = (dx * dy) * dz;
+  g->riemann = p->riemann;
+}
+
+static int check_params(const orc_params* p) {
+  if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return ORC_ERR_INVALID_ARG;
+  if (!(p->lx > 0) || !(p->ly > 0) || !(p->lz > 0)) return ORC_ERR_INVALID_ARG;
+  if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl < 1.0)) return ORC_ERR_INVALID_ARG;
+  if (p->riemann != ORC_HLLD && p->riemann != ORC_HLL) return ORC_ERR_INVALID_ARG;
+  if (p->integrator != ORC_RK2 && p->integrator != ORC_EULER) return ORC_ERR_INVALID_ARG;
+  return ORC_OK;
+}
+
+/* periodic neighbour indices (Sec. 2.6 grid, periodic in every direction) */
+static inline int up(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+static inline int dn(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+static inline long at(const grid_t* g, int i, int j, int k) {
+  return ((long)k * g->ny + j) * g->nx + i;
+}
+
+/* --------------------------------------------------------- point physics */
+
+/* S2: van Leer limited slope, harmonic mean of the one-sided differences when
+ * they share a sign, else zero (Sec. 2.3, second-order reconstruction). */
+double orc_vanleer(double dm, double dp) {
+  double s = dp * dm;
+  return s > 0.0 ? (2.0 * s) / (dp + dm) : 0.0;
+}
+
+/* Fast and slow magnetosonic speeds from a^2 = gamma p / rho, total and normal
+ * Alfven speeds (standard ideal-MHD wave speeds). */
+static double speed2_parts(double gamma, double rho, double p, double bn, double bt1,
+                           double bt2, double* s_out) {
+  double irho = 1.0 / rho;
+  double a2 = (gamma * p) * irho;
+  double bb = (bn * bn + bt1 * bt1) + bt2 * bt2;
+  double ca2 = bb * irho;
+  double cn2 = (bn * bn) * irho;
+  double s = a2 + ca2;
+  double disc = s * s - 4.0 * (a2 * cn2);
+  *s_out = s;
+  return disc > 0.0 ? disc : 0.0;
+}
+
+double orc_fast_speed(double gamma, double rho, double p, double bn, double bt1, double bt2) {
+  double s;
+  double disc = speed2_parts(gamma, rho, p, bn, bt1, bt2, &s);
+  return sqrt(0.5 * (s + sqrt(disc)));
+}
+
+double orc_slow_speed(double gamma, double rho, double p, double bn, double bt1, double bt2) {
+  double s;
+  double disc = speed2_parts(gamma, rho, p, bn, bt1, bt2, &s);
+  double c2 = 0.5 * (s - sqrt(disc));
+  return sqrt(c2 > 0.0 ? c2 : 0.0);
+}
+
+/* Conserved vector and physical flux of one face-frame state w = (rho, v_n, v_t1,
+ * v_t2, B_t1, B_t2, p) with normal field bn: total pressure p + B^2/2 inside the
+ * momentum flux (Sec. 2.1 and 2.3), energy E = p/(gamma-1) + rho v^2/2 + B^2/2. */
+static void phys(double igm1, const double* w, double bn, double* u, double* f, double* pt_out) {
+  double rho = w[0], un = w[1], v1 = w[2], v2 = w[3], b1 = w[4], b2 = w[5], p = w[6];
+  double v2sq = (un * un + v1 * v1) + v2 * v2;
+  double bb = (bn * bn + b1 * b1) + b2 * b2;
+  double pt = p + 0.5 * bb;
+  double e = (p * igm1 + 0.5 * (rho * v2sq)) + 0.5 * bb;
+  double vb = (un * bn + v1 * b1) + v2 * b2;
+  double mn = rho * un;
+  u[0] = rho;
+  u[1] = mn;
+  u[2] = rho * v1;
+  u[3] = rho * v2;
+  u[4] = e;
+  u[5] = b1;
+  u[6] = b2;
+  f[0] = mn;
+  f[1] = (mn * un + pt) - bn * bn;
+  f[2] = mn * v1 - bn * b1;
+  f[3] = mn * v2 - bn * b2;
+  f[4] = (e + pt) * un - bn * vb;
+  f[5] = un * b1 - bn * v1;
+  f[6] = un * b2 - bn * v2;
+  *pt_out = pt;
+}
+
+void orc_phys_flux(double gamma, const double w[7], double bn, double u[7], double f[7]) {
+  double pt;
+  phys(1.0 / (gamma - 1.0), w, bn, u, f, &pt);
+}
+
+/* Outer wave-speed bounds shared by HLL and HLLD. */
+static void outer_speeds(double gamma, const double* wl, const double* wr, double bn,
+                         double* sl, double* sr, double* cmax) {
+  double cfl = orc_fast_speed(gamma, wl[0], wl[6], bn, wl[4], wl[5]);
+  double cfr = orc_fast_speed(gamma, wr[0], wr[6], bn, wr[4], wr[5]);
+  double cfm = cfl > cfr ? cfl : cfr;
+  double umin = wl[1] < wr[1] ? wl[1] : wr[1];
+  double umax = wl[1] > wr[1] ? wl[1] : wr[1];
+  *sl = umin - cfm;
+  *sr = umax + cfm;
+  double al = fabs(*sl), ar = fabs(*sr);
+  *cmax = al > ar ? al : ar;
+}
+
+/* HLL: one intermediate state between S_L and S_R. */
+static void hll(double gamma, double igm1, const double* wl, const double* wr, double bn,
+                double* f, double* cmax) {
+  double ul[7], fl[7], ur[7], fr[7], ptl, ptr, sl, sr;
+  phys(igm1, wl, bn, ul, fl, &ptl);
+  phys(igm1, wr, bn, ur, fr, &ptr);
+  outer_speeds(gamma, wl, wr, bn, &sl, &sr, cmax);
+  if (sl >= 0.0) {
+    memcpy(f, fl, sizeof fl);
+  } else if (sr <= 0.0) {
+    memcpy(f, fr, sizeof fr);
+  } else {
+    double ih = 1.0 / (sr - sl);
+    double slr = sr * sl;
+    for (int q = 0; q < 7; ++q) f[q] = ((sr * fl[q] - sl * fr[q]) + slr * (ur[q] - ul[q])) * ih;
+  }
+}
+
+/* One side's single-star state of HLLD (Miyoshi & Kusano 2005): density,
+ * tangential velocity and field, and energy behind the fast wave S_a. */
+typedef struct {
+  double rho, v1, v2, b1, b2, e, vb, sq;
+  double u[7];
+} star_t;
+
+static void hlld_star(const double* w, double bn, double sa, double sm, double pts,
+                      const double* ua, double pta, star_t* st) {
+  const double eps = 1e-12;
+  double rho = w[0], un = w[1], v1 = w[2], v2 = w[3], b1 = w[4], b2 = w[5];
+  double sua = sa - un;  /* S_a - u_a */
+  double da = sua * rho; /* rho_a (S_a - u_a) */
+  double sam = sa - sm;  /* S_a - S_M */
+  double isam = 1.0 / sam;
+  double rhos = da * isam;
+  double t = da * sam;
+  double bn2 = bn * bn;
+  double den = t - bn2;
+  double v1s, v2s, b1s, b2s;
+  if (fabs(den) <= eps * (fabs(t) + bn2)) {
+    v1s = v1;
+    v2s = v2;
+    b1s = b1;
+    b2s = b2;
+  } else {
+    double iden = 1.0 / den;
+    double tv = (bn * (sm - un)) * iden;
+    double tb = (da * sua - bn2) * iden;
+    v1s = v1 - b1 * tv;
+    v2s = v2 - b2 * tv;
+    b1s = b1 * tb;
+    b2s = b2 * tb;
+  }
+  double vba = (un * bn + v1 * b1) + v2 * b2;
+  double vbs = (sm * bn + v1s * b1s) + v2s * b2s;
+  double es = (((sua * ua[4] - pta * un) + pts * sm) + bn * (vba - vbs)) * isam;
+  st->rho = rhos;
+  st->v1 = v1s;
+  st->v2 = v2s;
+  st->b1 = b1s;
+  st->b2 = b2s;
+  st->e = es;
+  st->vb = vbs;
+  st->u[0] = rhos;
+  st->u[1] = rhos * sm;
+  st->u[2] = rhos * v1s;
+  st->u[3] = rhos * v2s;
+  st->u[4] = es;
+  st->u[5] = b1s;
+  st->u[6] = b2s;
+}
+
+/* HLLD: four intermediate states separated by S_L, S*_L, S_M, S*_R, S_R. */
+static void hlld(double gamma, double igm1, const double* wl, const double* wr, double bn,
+                 double* f, double* cmax) {
+  double ul[7], fl[7], ur[7], fr[7], ptl, ptr, sl, sr;
+  phys(igm1, wl, bn, ul, fl, &ptl);
+  phys(igm1, wr, bn, ur, fr, &ptr);
+  outer_speeds(gamma, wl, wr, bn, &sl, &sr, cmax);
+  if (sl >= 0.0) {
+    memcpy(f, fl, sizeof fl);
+    return;
+  }
+  if (sr <= 0.0) {
+    memcpy(f, fr, sizeof fr);
+    return;
+  }
+  /* contact speed S_M and star total pressure, both over the same denominator */
+  double dl = (sl - wl[1]) * wl[0];
+  double dr = (sr - wr[1]) * wr[0];
+  double iden = 1.0 / (dr - dl);
+  double sm = (((dr * wr[1] - dl * wl[1]) - ptr) + ptl) * iden;
+  double pts = ((dr * ptl - dl * ptr) + (dr * dl) * (wr[1] - wl[1])) * iden;
+
+  star_t stl, str;
+  hlld_star(wl, bn, sl, sm, pts, ul, ptl, &stl);
+  hlld_star(wr, bn, sr, sm, pts, ur, ptr, &str);
+
+  double fsl[7], fsr[7];
+  for (int q = 0; q < 7; ++q) fsl[q] = fl[q] + sl * (stl.u[q] - ul[q]);
+  for (int q = 0; q < 7; ++q) fsr[q] = fr[q] + sr * (str.u[q] - ur[q]);
+
+  double sql = sqrt(stl.rho), sqr = sqrt(str.rho);
+  double abn = fabs(bn);
+  double ssl = sm - abn / sql;
+  double ssr = sm + abn / sqr;
+  if (ssl >= 0.0) {
+    memcpy(f, fsl, sizeof fsl);
+    return;
+  }
+  if (!(sm >= 0.0) && !(ssr >= 0.0)) {
+    memcpy(f, fsr, sizeof fsr);
+    return;
+  }
+  /* double-star states across the rotational discontinuities */
+  double sgn = bn > 0.0 ? 1.0 : (bn < 0.0 ? -1.0 : 0.0);
+  double isq = 1.0 / (sql + sqr);
+  double v1ss = ((sql * stl.v1 + sqr * str.v1) + (str.b1 - stl.b1) * sgn) * isq;
+  double v2ss = ((sql * stl.v2 + sqr * str.v2) + (str.b2 - stl.b2) * sgn) * isq;
+  double b1ss = ((sql * str.b1 + sqr * stl.b1) + (sql * sqr) * ((str.v1 - stl.v1) * sgn)) * isq;
+  double b2ss = ((sql * str.b2 + sqr * stl.b2) + (sql * sqr) * ((str.v2 - stl.v2) * sgn)) * isq;
+  double vbss = (sm * bn + v1ss * b1ss) + v2ss * b2ss;
+  if (sm >= 0.0) {
+    double ess = stl.e - (sql * (stl.vb - vbss)) * sgn;
+    double uss[7] = {stl.rho, stl.rho * sm, stl.rho * v1ss, stl.rho * v2ss, ess, b1ss, b2ss};
+    for (int q = 0; q < 7; ++q) f[q] = fsl[q] + ssl * (uss[q] - stl.u[q]);
+  } else {
+    double ess = str.e + (sqr * (str.vb - vbss)) * sgn;
+    double uss[7] = {str.rho, str.rho * sm, str.rho * v1ss, str.rho * v2ss, ess, b1ss, b2ss};
+    for (int q = 0; q < 7; ++q) f[q] = fsr[q] + ssr * (uss[q] - str.u[q]);
+  }
+}
+
+static void riemann(int solver, double gamma, double igm1, const double* wl, const double* wr,
+                    double bn, double* f, double* cmax) {
+  if (solver == ORC_HLL)
+    hll(gamma, igm1, wl, wr, bn, f, cmax);
+  else
+    hlld(gamma, igm1, wl, wr, bn, f, cmax);
+}
+
+void orc_riemann(int solver, double gamma, int n, const double* wl, const double* wr,
+                 const double* bn, double* flux, double* cmax) {
+  double igm1 = 1.0 / (gamma - 1.0);
+  for (int i = 0; i < n; ++i)
+    riemann(solver, gamma, igm1, wl + 7 * i, wr + 7 * i, bn[i], flux + 7 * i, cmax + i);
+}
+
+/* S7: upwinded choice between two candidate slopes by the sign of a mass flux. */
+static inline double upw(double s, double l, double r) {
+  return s > 0.0 ? l : (s < 0.0 ? r : 0.5 * (l + r));
+}
+
+/* E^c corner EMF in the (P, Q) plane at (p-1/2, q-1/2):
+ *   a1, a2: P-face EMFs at (p-1/2, q) and (p-1/2, q-1);
+ *   b1, b2: Q-face EMFs at (p, q-1/2) and (p-1, q-1/2);
+ *   cAB:    cell EMF -(v x B)_R at cell (p-1+A, q-1+B);
+ *   sq1, sq3: P-face mass fluxes at (p-1/2, q), (p-1/2, q-1);
+ *   sp1, sp3: Q-face mass fluxes at (p, q-1/2), (p-1, q-1/2).
+ * The mean of the four face EMFs is corrected by the upwinded derivatives of the
+ * EMF toward the corner along Q and along P (Gardiner & Stone 2005). */
+double orc_corner_emf(double a1, double a2, double b1, double b2, double c00, double c10,
+                      double c01, double c11, double sq1, double sq3, double sp1, double sp3) {
+  double dq1 = upw(sq1, c01 - b2, c11 - b1);
+  double dq3 = upw(sq3, b2 - c00, b1 - c10);
+  double dp1 = upw(sp1, c10 - a2, c11 - a1);
+  double dp3 = upw(sp3, a2 - c00, a1 - c01);
+  return 0.25 * ((((a1 + a2) + (b1 + b2)) + (dq3 - dq1)) + (dp3 - dp1));
+}
+
+/* --------------------------------------------------------------- stage */
+
+enum { W_RHO, W_VX, W_VY, W_VZ, W_BX, W_BY, W_BZ, W_P, NW };
+enum { F_RHO, F_MX, F_MY, F_MZ, F_EN, F_B1, F_B2, F_CMAX, NF };
+
+typedef struct {
+  double* w[NW];     /* primitives per cell */
+  double* f[3][NF];  /* per direction, the face at the low side of each cell */
+  double* er[3];     /* cell reference EMFs -(v x B)_x,y,z */
+  double* ed[3];     /* edge EMFs: E_x at (i, j-1/2, k-1/2), E_y at (i-1/2, j, k-1/2),
+                        E_z at (i-1/2, j-1/2, k) */
+  double* block;
+} work_t;
+
+static int work_alloc(work_t* w, long n) {
+  long nar = NW + 3 * NF + 3 + 3;
+  w->block = (double*)malloc(sizeof(double) * nar * n);
+  if (!w->block) return ORC_ERR_NOMEM;
+  double* p = w->block;
+  for (int q = 0; q < NW; ++q, p += n) w->w[q] = p;
+  for (int d = 0; d < 3; ++d)
+    for (int q = 0; q < NF; ++q, p += n) w->f[d][q] = p;
+  for (int d = 0; d < 3; ++d, p += n) w->er[d] = p;
+  for (int d = 0; d < 3; ++d, p += n) w->ed[d] = p;
+  return ORC_OK;
+}
+
+/* S1 on every cell.  Returns nonzero if any cell is non-physical. */
+static int prim_all(const grid_t* g, const orc_state* s, work_t* w) {
+  int bad = 0;
+#pragma omp parallel for reduction(| : bad) schedule(static)
+  for (int k = 0; k < g->nz; ++k)
+    for (int j = 0; j < g->ny; ++j)
+      for (int i = 0; i < g->nx; ++i) {
+        long c = at(g, i, j, k);
+        double bcx = 0.5 * (s->bx[c] + s->bx[at(g, up(i, g->nx), j, k)]);
+        double bcy = 0.5 * (s->by[c] + s->by[at(g, i, up(j, g->ny), k)]);
+        double bcz = 0.5 * (s->bz[c] + s->bz[at(g, i, j, up(k, g->nz))]);
+        double rho = s->rho[c];
+        double irho = 1.0 / rho;
+        double vx = s->mx[c] * irho, vy = s->my[c] * irho, vz = s->mz[c] * irho;
+        double ke = 0.5 * ((s->mx[c] * vx + s->my[c] * vy) + s->mz[c] * vz);
+        double me = 0.5 * ((bcx * bcx + bcy * bcy) + bcz * bcz);
+        double p = g->gm1 * ((s->en[c] - ke) - me);
+        w->w[W_RHO][c] = rho;
+        w->w[W_VX][c] = vx;
+        w->w[W_VY][c] = vy;
+        w->w[W_VZ][c] = vz;
+        w->w[W_BX][c] = bcx;
+        w->w[W_BY][c] = bcy;
+        w->w[W_BZ][c] = bcz;
+        w->w[W_P][c] = p;
+        if (!(rho > 0.0) || !(p > 0.0) || !isfinite(p) || !isfinite(vx) || !isfinite(vy) ||
+            !isfinite(vz) || !isfinite(bcx) || !isfinite(bcy) || !isfinite(bcz))
+          bad = 1;
+      }
+  return bad;
+}
+
+/* Face frame of direction d: (rho, v_n, v_t1, v_t2, B_t1, B_t2, p) with the
+ * cyclic tangential order x -> (y, z), y -> (z, x), z -> (x, y). */
+static const int frame[3][7] = {
+    {W_RHO, W_VX, W_VY, W_VZ, W_BY, W_BZ, W_P},
+    {W_RHO, W_VY, W_VZ, W_VX, W_BZ, W_BX, W_P},
+    {W_RHO, W_VZ, W_VX, W_VY, W_BX, W_BY, W_P},
+};
+/* grid-frame momentum component carried by face-frame m_n, m_t1, m_t2 */
+static const int mom_of[3][3] = {{F_MX, F_MY, F_MZ}, {F_MY, F_MZ, F_MX}, {F_MZ, F_MX, F_MY}};
+
+/* S2 + S3 for the faces at the low side of every cell along direction d. */
+static void faces(const grid_t* g, const orc_state* s, work_t* w, int d) {
+  const double* bnarr = d == 0 ? s->bx : (d == 1 ? s->by : s->bz);
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < g->nz; ++k)
+    for (int j = 0; j < g->ny; ++j)
+      for (int i = 0; i < g->nx; ++i) {
+        /* the four cells c-2, c-1, c, c+1 along d */
+        long c[4];
+        if (d == 0) {
+          int im1 = dn(i, g->nx);
+          c[0] = at(g, dn(im1, g->nx), j, k);
+          c[1] = at(g, im1, j, k);
+          c[2] = at(g, i, j, k);
+          c[3] = at(g, up(i, g->nx), j, k);
+        } else if (d == 1) {
+          int jm1 = dn(j, g->ny);
+          c[0] = at(g, i, dn(jm1, g->ny), k);
+          c[1] = at(g, i, jm1, k);
+          c[2] = at(g, i, j, k);
+          c[3] = at(g, i, up(j, g->ny), k);
+        } else {
+          int km1 = dn(k, g->nz);
+          c[0] = at(g, i, j, dn(km1, g->nz));
+          c[1] = at(g, i, j, km1);
+          c[2] = at(g, i, j, k);
+          c[3] = at(g, i, j, up(k, g->nz));
+        }
+        double wl[7], wr[7], fl[7], cmax;
+        for (int v = 0; v < 7; ++v) {
+          const double* q = w->w[frame[d][v]];
+          double q0 = q[c[0]], q1 = q[c[1]], q2 = q[c[2]], q3 = q[c[3]];
+          double sl = orc_vanleer(q1 - q0, q2 - q1);
+          double sr = orc_vanleer(q2 - q1, q3 - q2);
+          wl[v] = q1 + 0.5 * sl;
+          wr[v] = q2 - 0.5 * sr;
+        }
+        long o = c[2];
+        riemann(g->riemann, g->gamma, g->igm1, wl, wr, bnarr[o], fl, &cmax);
+        w->f[d][F_RHO][o] = fl[0];
+        w->f[d][mom_of[d][0]][o] = fl[1];
+        w->f[d][mom_of[d][1]][o] = fl[2];
+        w->f[d][mom_of[d][2]][o] = fl[3];
+        w->f[d][F_EN][o] = fl[4];
+        w->f[d][F_B1][o] = fl[5];
+        w->f[d][F_B2][o] = fl[6];
+        w->f[d][F_CMAX][o] = cmax;
+      }
+}
+
+/* S7: cell reference EMFs and the three edge EMFs of every cell. */
+static void emfs(const grid_t* g, work_t* w) {
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < g->n; ++c) {
+    double vx = w->w[W_VX][c], vy = w->w[W_VY][c], vz = w->w[W_VZ][c];
+    double bx = w->w[W_BX][c], by = w->w[W_BY][c], bz = w->w[W_BZ][c];
+    w->er[0][c] = vz * by - vy * bz;
+    w->er[1][c] = vx * bz - vz * bx;
+    w->er[2][c] = vy * bx - vx * by;
+  }
+  /* Face EMFs: on a face of direction n with cyclic tangents (t1, t2),
+   * E_t2 = -F[B_t1] and E_t1 = +F[B_t2]. */
+  double* const* fx = w->f[0];
+  double* const* fy = w->f[1];
+  double* const* fz = w->f[2];
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < g->nz; ++k) {
+    int km = dn(k, g->nz);
+    for (int j = 0; j < g->ny; ++j) {
+      int jm = dn(j, g->ny);
+      for (int i = 0; i < g->nx; ++i) {
+        int im = dn(i, g->nx);
+        long c = at(g, i, j, k);
+        /* E_z at (i-1/2, j-1/2, k): P = x, Q = y */
+        {
+          long cjm = at(g, i, jm, k), cim = at(g, im, j, k), cimjm = at(g, im, jm, k);
+          w->ed[2][c] = orc_corner_emf(-fx[F_B1][c], -fx[F_B1][cjm], fy[F_B2][c], fy[F_B2][cim],
+                                       w->er[2][cimjm], w->er[2][cjm], w->er[2][cim], w->er[2][c],
+                                       fx[F_RHO][c], fx[F_RHO][cjm], fy[F_RHO][c], fy[F_RHO][cim]);
+        }
+        /* E_x at (i, j-1/2, k-1/2): P = y, Q = z */
+        {
+          long ckm = at(g, i, j, km), cjm = at(g, i, jm, k), cjmkm = at(g, i, jm, km);
+          w->ed[0][c] = orc_corner_emf(-fy[F_B1][c], -fy[F_B1][ckm], fz[F_B2][c], fz[F_B2][cjm],
+                                       w->er[0][cjmkm], w->er[0][ckm], w->er[0][cjm], w->er[0][c],
+                                       fy[F_RHO][c], fy[F_RHO][ckm], fz[F_RHO][c], fz[F_RHO][cjm]);
+        }
+        /* E_y at (i-1/2, j, k-1/2): P = z, Q = x */
+        {
+          long cim = at(g, im, j, k), ckm = at(g, i, j, km), cimkm = at(g, im, j, km);
+          w->ed[1][c] = orc_corner_emf(-fz[F_B1][c], -fz[F_B1][cim], fx[F_B2][c], fx[F_B2][ckm],
+                                       w->er[1][cimkm], w->er[1][cim], w->er[1][ckm], w->er[1][c],
+                                       fz[F_RHO][c], fz[F_RHO][cim], fx[F_RHO][c], fx[F_RHO][ckm]);
+        }
+      }
+    }
+  }
+}
+
+/* One application of the stage operator S_dt (steps S1-S8) to src, written to
+ * dst; if base is given, dst = 0.5 S_dt(src) + 0.5 base (second RK2 stage; base
+ * and dst may be the same arrays).  If maxinv is given it receives the CFL
+ * maximum of eq. (cfl) measured on src. */
+static int stage(const grid_t* g, const orc_state* src, const orc_state* base, orc_state* dst,
+                 double dt, double* maxinv, work_t* w) {
+  int bad = prim_all(g, src, w);
+  for (int d = 0; d < 3; ++d) faces(g, src, w, d);
+  emfs(g, w);
+  double tx = dt * g->idl[0], ty = dt * g->idl[1], tz = dt * g->idl[2];
+  double mx = 0.0;
+  double* const* fx = w->f[0];
+  double* const* fy = w->f[1];
+  double* const* fz = w->f[2];
+  const double* us[5] = {src->rho, src->mx, src->my, src->mz, src->en};
+  double* ud[5] = {dst->rho, dst->mx, dst->my, dst->mz, dst->en};
+  const double* ub[5] = {0};
+  if (base) {
+    ub[0] = base->rho;
+    ub[1] = base->mx;
+    ub[2] = base->my;
+    ub[3] = base->mz;
+    ub[4] = base->en;
+  }
+#pragma omp parallel for reduction(max : mx) schedule(static)
+  for (int k = 0; k < g->nz; ++k) {
+    int kp = up(k, g->nz);
+    for (int j = 0; j < g->ny; ++j) {
+      int jp = up(j, g->ny);
+      for (int i = 0; i < g->nx; ++i) {
+        int ip = up(i, g->nx);
+        long c = at(g, i, j, k);
+        long cxp = at(g, ip, j, k), cyp = at(g, i, jp, k), czp = at(g, i, j, kp);
+        /* S5: flux divergence, x then y then z */
+        for (int q = 0; q < 5; ++q) {
+          double v = ((us[q][c] - tx * (fx[q][cxp] - fx[q][c])) - ty * (fy[q][cyp] - fy[q][c])) -
+                     tz * (fz[q][czp] - fz[q][c]);
+          ud[q][c] = base ? 0.5 * v + 0.5 * ub[q][c] : v;
+        }
+        /* S8: discrete Stokes on each face */
+        const double* ex = w->ed[0];
+        const double* ey = w->ed[1];
+        const double* ez = w->ed[2];
+        double bxn = (src->bx[c] - ty * (ez[cyp] - ez[c])) + tz * (ey[czp] - ey[c]);
+        double byn = (src->by[c] - tz * (ex[czp] - ex[c])) + tx * (ez[cxp] - ez[c]);
+        double bzn = (src->bz[c] - tx * (ey[cxp] - ey[c])) + ty * (ex[cyp] - ex[c]);
+        if (base) {
+          bxn = 0.5 * bxn + 0.5 * base->bx[c];
+          byn = 0.5 * byn + 0.5 * base->by[c];
+          bzn = 0.5 * bzn + 0.5 * base->bz[c];
+        }
+        dst->bx[c] = bxn;
+        dst->by[c] = byn;
+        dst->bz[c] = bzn;
+        /* eq. (cfl): largest signal speed of the cell along each direction */
+        double cx = fx[F_CMAX][c] > fx[F_CMAX][cxp] ? fx[F_CMAX][c] : fx[F_CMAX][cxp];
+        double cy = fy[F_CMAX][c] > fy[F_CMAX][cyp] ? fy[F_CMAX][c] : fy[F_CMAX][cyp];
+        double cz = fz[F_CMAX][c] > fz[F_CMAX][czp] ? fz[F_CMAX][c] : fz[F_CMAX][czp];
+        double inv = ((cx * g->idl[0]) + cy * g->idl[1]) + cz * g->idl[2];
+        if (inv > mx) mx = inv;
+      }
+    }
+  }
+  if (maxinv) *maxinv = mx;
+  return bad;
+}
+
+/* ---------------------------------------------------------------- public */
+
+static int state_alloc(orc_state* s, long n, double** block) {
+  *block = (double*)malloc(sizeof(double) * 8 * n);
+  if (!*block) return ORC_ERR_NOMEM;
+  double* p = *block;
+  s->rho = p;
+  s->mx = p + n;
+  s->my = p + 2 * n;
+  s->mz = p + 3 * n;
+  s->en = p + 4 * n;
+  s->bx = p + 5 * n;
+  s->by = p + 6 * n;
+  s->bz = p + 7 * n;
+  return ORC_OK;
+}
+
+int orc_max_invdt(const orc_params* p, const orc_state* s, double* out) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  grid_t g;
+  grid_init(&g, p);
+  work_t w;
+  if (work_alloc(&w, g.n)) return ORC_ERR_NOMEM;
+  int bad = prim_all(&g, s, &w);
+  for (int d = 0; d < 3; ++d) faces(&g, s, &w, d);
+  double mx = 0.0;
+#pragma omp parallel for reduction(max : mx) schedule(static)
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        long c = at(&g, i, j, k);
+        long cxp = at(&g, up(i, g.nx), j, k), cyp = at(&g, i, up(j, g.ny), k),
+             czp = at(&g, i, j, up(k, g.nz));
+        double* const* fx = w.f[0];
+        double* const* fy = w.f[1];
+        double* const* fz = w.f[2];
+        double cx = fx[F_CMAX][c] > fx[F_CMAX][cxp] ? fx[F_CMAX][c] : fx[F_CMAX][cxp];
+        double cy = fy[F_CMAX][c] > fy[F_CMAX][cyp] ? fy[F_CMAX][c] : fy[F_CMAX][cyp];
+        double cz = fz[F_CMAX][c] > fz[F_CMAX][czp] ? fz[F_CMAX][c] : fz[F_CMAX][czp];
+        double inv = ((cx * g.idl[0]) + cy * g.idl[1]) + cz * g.idl[2];
+        if (inv > mx) mx = inv;
+      }
+  free(w.block);
+  *out = mx;
+  return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+/* step to take this cycle: the CFL step, clipped so as not to pass t_stop */
+static double clip_dt(double dt, double t, double t_stop) {
+  if (t_stop > 0.0) {
+    double rem = t_stop - t;
+    if (dt > rem) dt = rem;
+    if (!(dt > 0.0)) dt = 0.0;
+  }
+  return dt;
+}
+
+int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int nsteps,
+             double t_stop) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!s || !t || !dt_next || nsteps < 0) return ORC_ERR_INVALID_ARG;
+  grid_t g;
+  grid_init(&g, p);
+  if (!(*dt_next > 0.0)) {
+    double mi;
+    rc = orc_max_invdt(p, s, &mi);
+    if (rc) return rc;
+    *dt_next = p->cfl / mi;
+  }
+  work_t w;
+  orc_state tmp;
+  double* tblock;
+  if (work_alloc(&w, g.n)) return ORC_ERR_NOMEM;
+  if (state_alloc(&tmp, g.n, &tblock)) {
+    free(w.block);
+    return ORC_ERR_NOMEM;
+  }
+  int bad = 0;
+  for (int n = 0; n < nsteps; ++n) {
+    double dt = clip_dt(*dt_next, *t, t_stop);
+    double mi = 0.0;
+    /* stage 1: U_1 = S_dt(U_0)  (w_1 = 1, w0_1 = 0) */
+    bad |= stage(&g, s, NULL, &tmp, dt, &mi, &w);
+    if (p->integrator == ORC_RK2) {
+      /* stage 2: U^{n+1} = 1/2 S_dt(U_1) + 1/2 U_0 */
+      bad |= stage(&g, &tmp, s, s, dt, NULL, &w);
+    } else {
+      memcpy(s->rho, tmp.rho, sizeof(double) * g.n);
+      memcpy(s->mx, tmp.mx, sizeof(double) * g.n);
+      memcpy(s->my, tmp.my, sizeof(double) * g.n);
+      memcpy(s->mz, tmp.mz, sizeof(double) * g.n);
+      memcpy(s->en, tmp.en, sizeof(double) * g.n);
+      memcpy(s->bx, tmp.bx, sizeof(double) * g.n);
+      memcpy(s->by, tmp.by, sizeof(double) * g.n);
+      memcpy(s->bz, tmp.bz, sizeof(double) * g.n);
+    }
+    *t += dt;
+    *dt_next = p->cfl / mi;
+  }
+  free(w.block);
+  free(tblock);
+  return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+/* Neumaier-compensated running sum. */
+typedef struct {
+  double s, c;
+} ksum_t;
+static inline void kadd(ksum_t* a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+
+int orc_diagnostics(const orc_params* p, const orc_state* s, double out[10]) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  grid_t g;
+  grid_init(&g, p);
+  ksum_t acc[8];
+  memset(acc, 0, sizeof acc);
+  ksum_t d2 = {0, 0};
+  double dmax = 0.0;
+  const double* arr[8] = {s->rho, s->mx, s->my, s->mz, s->en, s->bx, s->by, s->bz};
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        long c = at(&g, i, j, k);
+        for (int q = 0; q < 8; ++q) kadd(&acc[q], arr[q][c]);
+        double div = ((s->bx[at(&g, up(i, g.nx), j, k)] - s->bx[c]) * g.idl[0] +
+                      (s->by[at(&g, i, up(j, g.ny), k)] - s->by[c]) * g.idl[1]) +
+                     (s->bz[at(&g, i, j, up(k, g.nz))] - s->bz[c]) * g.idl[2];
+        double a = fabs(div);
+        if (a > dmax) dmax = a;
+        kadd(&d2, div * div);
+      }
+  for (int q = 0; q < 8; ++q) out[q] = (acc[q].s + acc[q].c) * g.dv;
+  out[8] = dmax;
+  out[9] = sqrt((d2.s + d2.c) / (double)g.n);
+  return ORC_OK;
+}

@@ -1,0 +1,89 @@
+/*
+ * mhd_oracle.h -- plain FP64 CPU reference of the Godunov ideal-MHD cell update
+ * (Lesur et al., "IDEFIX: a versatile performance-portable Godunov code for
+ * astrophysical flows", arXiv:2304.13746).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU path; only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may load it.
+ * It shares no code, header or table with the GPU library.
+ *
+ * Grid: uniform Cartesian, periodic in x, y and z (Sec. 2.6).  Arrays are dense
+ * [nz][ny][nx] with x fastest.  Cell arrays hold (rho, m_x, m_y, m_z, E); face
+ * arrays hold B_x at (i-1/2, j, k), B_y at (i, j-1/2, k), B_z at (i, j, k-1/2)
+ * (face-centred constrained transport, Sec. 2.4).
+ */
+#ifndef MHD_ORACLE_H
+#define MHD_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_HLLD = 0, ORC_HLL = 1 };
+enum { ORC_RK2 = 0, ORC_EULER = 1 };
+
+enum {
+  ORC_OK = 0,
+  ORC_ERR_INVALID_ARG = -1,
+  ORC_ERR_NOMEM = -2,
+  ORC_ERR_NONPHYSICAL = -4
+};
+
+typedef struct {
+  int nx, ny, nz;      /* cells per direction, >= 1 */
+  double lx, ly, lz;   /* box lengths; dl_d = l_d / n_d */
+  double gamma;        /* adiabatic index, > 1 */
+  double cfl;          /* sigma_CFL of eq. (cfl), in (0, 1) */
+  int riemann;         /* ORC_HLLD or ORC_HLL */
+  int integrator;      /* ORC_RK2 or ORC_EULER (Tab. weights) */
+} orc_params;
+
+typedef struct {
+  double *rho, *mx, *my, *mz, *en; /* cell-centred conserved variables */
+  double *bx, *by, *bz;            /* face-centred magnetic field */
+} orc_state;
+
+/* Max over the volume of sum_d c_max,d / dl_d (eq. cfl) for the given state. */
+int orc_max_invdt(const orc_params* p, const orc_state* s, double* out);
+
+/* Advance nsteps cycles in place.  *dt_next is the step to use for the first
+ * cycle (pass <= 0 to compute it from the state); on return it holds the CFL
+ * step measured during the first stage of the last cycle.  t_stop > 0 clips each
+ * cycle's step to t_stop - t (never below zero). */
+int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next,
+             int nsteps, double t_stop);
+
+/* Diagnostics: out[0] mass, out[1..3] momentum, out[4] energy, out[5..7] face-B
+ * totals (each times the cell volume, compensated sums), out[8] max |div B|,
+ * out[9] rms div B. */
+int orc_diagnostics(const orc_params* p, const orc_state* s, double out[10]);
+
+/* ---- single building blocks, exported so tests can pin them ---- */
+
+/* van Leer limited slope from the backward and forward differences. */
+double orc_vanleer(double dm, double dp);
+
+/* Fast magnetosonic speed of a state (rho, p, Bn, Bt1, Bt2). */
+double orc_fast_speed(double gamma, double rho, double p, double bn, double bt1, double bt2);
+/* Slow magnetosonic speed (only used to pin the speeds of the linear-wave test). */
+double orc_slow_speed(double gamma, double rho, double p, double bn, double bt1, double bt2);
+
+/* Riemann solve on n faces.  wl, wr: n x 7 primitive face states in the face frame
+ * (rho, v_n, v_t1, v_t2, B_t1, B_t2, p); bn: n normal fields.  flux: n x 7 in the
+ * face frame (rho, m_n, m_t1, m_t2, E, B_t1, B_t2); cmax: n fastest |speeds|. */
+void orc_riemann(int solver, double gamma, int n, const double* wl, const double* wr,
+                 const double* bn, double* flux, double* cmax);
+
+/* Physical flux and conserved vector of one face-frame state. */
+void orc_phys_flux(double gamma, const double w[7], double bn, double u[7], double f[7]);
+
+/* Upwind-CT corner EMF from its four face EMFs, four cell reference EMFs and the
+ * four mass fluxes that pick the upwind side. */
+double orc_corner_emf(double a1, double a2, double b1, double b2,
+                      double c00, double c10, double c01, double c11,
+                      double sq1, double sq3, double sp1, double sp3);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
