@@ -1,0 +1,133 @@
+/*
+ * mhd.h -- C ABI of the MI355X (gfx950) ideal-MHD box library, libmhd.so.
+ *
+ * One context advances one periodic, uniform Cartesian box of the ideal-MHD
+ * equations (Lesur et al. 2023, arXiv:2304.13746, Sec. 2.1, eqs. cont, mom, ind,
+ * energy with viscosity, gravity, resistivity and conduction set to zero) with the
+ * Godunov finite-volume cycle of Sec. 2.2-2.7:
+ *   conserved U = (rho, rho v, E) at cell centres and B on cell faces (Sec. 2.2,
+ *   2.4); per stage: primitive reconstruction with the van Leer limiter (Sec. 2.3),
+ *   an HLLD or HLL Riemann solve on every x, y and z face (Sec. 2.3), corner EMFs
+ *   by the upwind-by-contact E^c scheme (Sec. 2.4), the flux-divergence update of U
+ *   and the constrained-transport update of face B (eq. ind_short); stages combined
+ *   as U_s = w_s U* + w0_s U_0 (Sec. 2.7, Tab. weights); time step from eq. (cfl).
+ * Energy is E = p/(gamma-1) + rho v^2/2 + B^2/2, dimensionless units without 4 pi.
+ *
+ * Memory.  The caller owns every device allocation.  A context borrows one device
+ * workspace (size from mhd_workspace_bytes) and keeps the box state, the step size
+ * and all scratch in it; the library allocates no device memory.  State views are
+ * eight device arrays, each dense [nz][ny][nx] with x fastest, of the context's
+ * precision (double for MHD_FP64, float for MHD_FP32):
+ *   rho, mx, my, mz, en : cell-centred density, momentum, total energy;
+ *   bx, by, bz          : face-centred field, bx[k][j][i] at (i-1/2, j, k),
+ *                         by at (i, j-1/2, k), bz at (i, j, k-1/2).
+ * Views are copied in and out (device to device), so they may be freed after the
+ * call returns.
+ *
+ * Streams and errors.  Every call enqueues work on the context's stream.
+ * mhd_step is asynchronous: it does no host synchronisation and no allocation, so
+ * it may be captured into a HIP graph.  Non-physical states found on the device
+ * (rho <= 0, p <= 0 or a non-finite value) are latched in the workspace and
+ * reported by the next synchronising call (mhd_get_state, mhd_get_diagnostics).
+ * No C++ exception crosses this interface.  A context is used by one host thread
+ * at a time; contexts are independent.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MHD_OK 0
+#define MHD_ERR_INVALID_ARG (-1)  /* bad parameter, null pointer or bad size */
+#define MHD_ERR_WORKSPACE (-2)    /* workspace missing, misaligned or too small */
+#define MHD_ERR_HIP (-3)          /* a HIP runtime call failed */
+#define MHD_ERR_NONPHYSICAL (-4)  /* rho <= 0, p <= 0 or non-finite value met */
+#define MHD_ERR_UNSUPPORTED (-5)  /* option combination not built */
+
+typedef enum { MHD_FP64 = 0, MHD_FP32 = 1 } mhd_precision;
+typedef enum { MHD_HLLD = 0, MHD_HLL = 1 } mhd_riemann;       /* Sec. 2.3 */
+typedef enum { MHD_EMF_EC = 0 } mhd_emf;                      /* E^c, Sec. 2.4 default */
+typedef enum { MHD_RK2 = 0, MHD_EULER = 1 } mhd_integrator;   /* Tab. weights */
+
+typedef struct mhd_ctx mhd_ctx; /* opaque */
+
+typedef struct {
+  int nx, ny, nz;         /* cells per direction, each in [1, 4096] */
+  double lx, ly, lz;      /* box lengths > 0; cell size dl_d = l_d / n_d */
+  double gamma;           /* adiabatic index > 1 */
+  double cfl;             /* sigma_CFL of eq. (cfl), in (0, 1); no dimension factor */
+  int precision;          /* mhd_precision: storage and arithmetic type */
+  int riemann;            /* mhd_riemann */
+  int emf;                /* mhd_emf */
+  int integrator;         /* mhd_integrator */
+  void* workspace;        /* device pointer, 256-byte aligned, BORROWED */
+  size_t workspace_bytes; /* >= mhd_workspace_bytes(this) */
+  void* stream;           /* hipStream_t to enqueue on (NULL: default stream) */
+  int tile;               /* kernel tile variant, 0 = default for the precision */
+  int zchunk;             /* z-planes per thread block, 0 = automatic */
+} mhd_params;
+
+typedef struct {
+  void *rho, *mx, *my, *mz, *en; /* cell-centred, device pointers */
+  void *bx, *by, *bz;            /* face-centred, device pointers */
+} mhd_state_view;
+
+typedef struct {
+  double mass;     /* sum rho dV */
+  double mom[3];   /* sum m dV */
+  double energy;   /* sum E dV */
+  double bflux[3]; /* sum of face B times dV, per component */
+  double divb_max; /* max over cells of |div B| (discrete Stokes divergence) */
+  double divb_rms; /* root mean square of div B over cells */
+  unsigned status; /* latched device status bits (0 = fine) */
+} mhd_diag;
+
+/* Device bytes a context with these parameters needs (only the grid, precision
+ * and tile fields are read).  Returns 0 if the grid is invalid. */
+size_t mhd_workspace_bytes(const mhd_params* params);
+
+/* Validate params and build a context on the borrowed workspace.  *out receives
+ * the context (host memory owned by the library until mhd_destroy).  Errors:
+ * MHD_ERR_INVALID_ARG, MHD_ERR_WORKSPACE, MHD_ERR_UNSUPPORTED. */
+int mhd_create(const mhd_params* params, mhd_ctx** out);
+
+/* Copy the state from src (device arrays, see above) into the context and set the
+ * time t.  dt_next > 0 is the step of the next cycle; dt_next <= 0 computes it
+ * from the state by eq. (cfl) on the device.  Asynchronous. */
+int mhd_set_state(mhd_ctx* ctx, const mhd_state_view* src, double t, double dt_next);
+
+/* Advance nsteps cycles (Sec. 2.7).  The step of each cycle is the CFL step
+ * measured during the first stage of the previous cycle; t_stop > 0 clips it so
+ * that t never passes t_stop (later cycles then have zero step).  Asynchronous,
+ * allocation-free, capture-safe. */
+int mhd_step(mhd_ctx* ctx, int nsteps, double t_stop);
+
+/* Copy the state out into dst (device arrays) and return t and the step of the
+ * next cycle.  Synchronises the stream.  Returns MHD_ERR_NONPHYSICAL (after the
+ * copy) if a non-physical value was met since the last set_state. */
+int mhd_get_state(mhd_ctx* ctx, const mhd_state_view* dst, double* t, double* dt_next);
+
+/* Conserved totals with compensated FP64 sums and div B statistics of the current
+ * state.  Synchronises the stream. */
+int mhd_get_diagnostics(mhd_ctx* ctx, mhd_diag* out);
+
+/* Advance n contexts by nsteps[i] cycles each with persistent launches on one
+ * stream (every context must share precision, solver and integrator).  Each box
+ * keeps its own step size.  Asynchronous. */
+int mhd_step_batch(mhd_ctx* const* ctxs, const int* nsteps, int n, void* stream);
+
+/* Release the context (not the borrowed workspace).  Safe on NULL. */
+int mhd_destroy(mhd_ctx* ctx);
+
+/* Text for a status code. */
+const char* mhd_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHD_H */

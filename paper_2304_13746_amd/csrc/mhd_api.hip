@@ -1,0 +1,445 @@
+// mhd_api.hip -- C ABI of libmhd: contexts on borrowed workspaces, cycle
+// control on the device, state copies and diagnostics.  See include/mhd.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "../../include/mhd.h"
+#include "mhd_internal.h"
+
+using namespace mhd;
+
+struct mhd_ctx {
+  mhd_params p;
+  hipStream_t stream;
+  int device;
+  size_t elem;       // bytes per value: 8 (FP64) or 4 (FP32)
+  long long ncell;
+  double idl[3];     // 1 / (l_d / n_d)
+  double dv;         // cell volume
+  void* buf[2][8];   // two state buffers of 8 fields
+  int cur;           // buffer holding the state
+  Scalars* sc;       // device scalars
+  double* diag_part; // per-block diagnostic partials
+  int tile, lz;
+  int diag_blocks;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDiagBlocks = 512;
+constexpr int kDiagVals = 20;  // 9 sums as (sum, compensation) pairs + max + pad
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool grid_ok(const mhd_params* p) {
+  return p && p->nx >= 1 && p->ny >= 1 && p->nz >= 1 && p->nx <= 4096 && p->ny <= 4096 &&
+         p->nz <= 4096;
+}
+
+int default_tile(int precision) { return precision == MHD_FP32 ? TILE_16x16 : TILE_16x16; }
+
+size_t field_bytes(const mhd_params* p) {
+  size_t e = p->precision == MHD_FP32 ? 4 : 8;
+  return align_up((size_t)p->nx * p->ny * p->nz * e);
+}
+
+// ---- cycle control kernels (one thread): everything stays on the device
+
+__device__ double clip_step(double dt, double t, double t_stop) {
+  if (t_stop > 0.0) {
+    double rem = t_stop - t;
+    if (dt > rem) dt = rem;
+    if (!(dt > 0.0)) dt = 0.0;
+  }
+  return dt;
+}
+
+__global__ void k_set(Scalars* s, double t, double dt_next, double cfl) {
+  st_agent(&s->t, t);
+  st_agent(&s->dt_next, dt_next);
+  st_agent(&s->dt, 0.0);
+  st_agent(&s->cfl, cfl);
+  st_agent(&s->invdt_bits, 0ull);
+  st_agent(&s->status, 0u);
+}
+
+__device__ double invdt_max(Scalars* s) {
+  return __longlong_as_double((long long)ld_agent(&s->invdt_bits));
+}
+
+// dt_next from the CFL maximum just measured
+__global__ void k_init_dt(Scalars* s) {
+  st_agent(&s->dt_next, ld_agent(&s->cfl) / invdt_max(s));
+  st_agent(&s->invdt_bits, 0ull);
+}
+
+__global__ void k_begin(Scalars* s, double t_stop) {
+  st_agent(&s->dt, clip_step(ld_agent(&s->dt_next), ld_agent(&s->t), t_stop));
+  st_agent(&s->invdt_bits, 0ull);
+}
+
+// end of a cycle: advance t, take the step measured during its first stage,
+// clip the next cycle's step
+__global__ void k_end(Scalars* s, double t_stop) {
+  const double t = ld_agent(&s->t) + ld_agent(&s->dt);
+  const double dtn = ld_agent(&s->cfl) / invdt_max(s);
+  st_agent(&s->t, t);
+  st_agent(&s->dt_next, dtn);
+  st_agent(&s->dt, clip_step(dtn, t, t_stop));
+  st_agent(&s->invdt_bits, 0ull);
+}
+
+// ---- diagnostics: Neumaier-compensated sums in FP64
+
+struct Ksum {
+  double s, c;
+};
+__device__ __forceinline__ void kadd(Ksum& a, double x) {
+  double t = a.s + x;
+  if (fabs(a.s) >= fabs(x))
+    a.c += (a.s - t) + x;
+  else
+    a.c += (x - t) + a.s;
+  a.s = t;
+}
+
+template <typename R>
+__global__ void k_diag_partial(const R* rho, const R* mx, const R* my, const R* mz, const R* en,
+                               const R* bx, const R* by, const R* bz, int nx, int ny, int nz,
+                               double idx, double idy, double idz, double* part) {
+  const long long n = (long long)nx * ny * nz;
+  Ksum acc[9];
+  for (int q = 0; q < 9; ++q) acc[q] = {0.0, 0.0};
+  double dmax = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(c % nx);
+    long long r = c / nx;
+    int j = (int)(r % ny);
+    int k = (int)(r / ny);
+    kadd(acc[0], (double)rho[c]);
+    kadd(acc[1], (double)mx[c]);
+    kadd(acc[2], (double)my[c]);
+    kadd(acc[3], (double)mz[c]);
+    kadd(acc[4], (double)en[c]);
+    kadd(acc[5], (double)bx[c]);
+    kadd(acc[6], (double)by[c]);
+    kadd(acc[7], (double)bz[c]);
+    long long cxp = c - i + (i + 1 == nx ? 0 : i + 1);
+    long long cyp = c + (long long)((j + 1 == ny ? 0 : j + 1) - j) * nx;
+    long long czp = c + (long long)((k + 1 == nz ? 0 : k + 1) - k) * nx * ny;
+    double div = (((double)bx[cxp] - (double)bx[c]) * idx + ((double)by[cyp] - (double)by[c]) * idy) +
+                 ((double)bz[czp] - (double)bz[c]) * idz;
+    kadd(acc[8], div * div);
+    double ad = fabs(div);
+    dmax = ad > dmax ? ad : dmax;
+  }
+  // block combine in a fixed order through LDS
+  __shared__ double ss[256][19];
+  for (int q = 0; q < 9; ++q) {
+    ss[threadIdx.x][2 * q] = acc[q].s;
+    ss[threadIdx.x][2 * q + 1] = acc[q].c;
+  }
+  ss[threadIdx.x][18] = dmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Ksum tot[9];
+    for (int q = 0; q < 9; ++q) tot[q] = {0.0, 0.0};
+    double m = 0.0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      for (int q = 0; q < 9; ++q) {
+        kadd(tot[q], ss[t][2 * q]);
+        kadd(tot[q], ss[t][2 * q + 1]);
+      }
+      m = ss[t][18] > m ? ss[t][18] : m;
+    }
+    double* out = part + (size_t)blockIdx.x * kDiagVals;
+    for (int q = 0; q < 9; ++q) {
+      st_agent(out + 2 * q, tot[q].s);
+      st_agent(out + 2 * q + 1, tot[q].c);
+    }
+    st_agent(out + 18, m);
+  }
+}
+
+__global__ void k_diag_final(const double* part, int nblocks, double dv, double ncell, Scalars* s) {
+  Ksum tot[9];
+  for (int q = 0; q < 9; ++q) tot[q] = {0.0, 0.0};
+  double m = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double* p = part + (size_t)b * kDiagVals;
+    for (int q = 0; q < 9; ++q) {
+      kadd(tot[q], ld_agent(p + 2 * q));
+      kadd(tot[q], ld_agent(p + 2 * q + 1));
+    }
+    const double pm = ld_agent(p + 18);
+    m = pm > m ? pm : m;
+  }
+  for (int q = 0; q < 8; ++q) st_agent(&s->diag[q], (tot[q].s + tot[q].c) * dv);
+  st_agent(&s->diag[8], m);
+  st_agent(&s->diag[9], sqrt((tot[8].s + tot[8].c) / ncell));
+}
+
+int hip_fail(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_HIP; }
+
+void fields_of(const mhd_state_view* v, void* out[8]) {
+  out[0] = v->rho; out[1] = v->mx; out[2] = v->my; out[3] = v->mz;
+  out[4] = v->en; out[5] = v->bx; out[6] = v->by; out[7] = v->bz;
+}
+
+hipError_t launch_stage(mhd_ctx* c, int mode, int src, int dst) {
+  StageLaunch l;
+  for (int f = 0; f < 8; ++f) {
+    l.src[f] = c->buf[src][f];
+    l.dst[f] = c->buf[dst][f];
+  }
+  l.nx = c->p.nx;
+  l.ny = c->p.ny;
+  l.nz = c->p.nz;
+  l.lz = c->lz;
+  for (int d = 0; d < 3; ++d) l.idl[d] = c->idl[d];
+  l.gamma = c->p.gamma;
+  l.sc = c->sc;
+  l.tile = c->tile;
+  l.solver = c->p.riemann;
+  l.mode = mode;
+  return c->p.precision == MHD_FP32 ? stage_f32(l, c->stream, false) : stage_f64(l, c->stream, false);
+}
+
+int choose_lz(int tile, int nx, int ny, int nz) {
+  int tx, ty;
+  tile_dims(tile, &tx, &ty);
+  long long tiles = (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+  // aim for >= 2048 blocks (8 per CU), chunks of at least 16 planes
+  long long want = (2048 + tiles - 1) / tiles;
+  int lz = (int)((nz + want - 1) / want);
+  if (lz < 16) lz = 16;
+  if (lz > nz) lz = nz;
+  return lz;
+}
+
+}  // namespace
+
+namespace mhd {
+int tile_dims(int tile, int* tx, int* ty) {
+  if (tile == TILE_16x16) { *tx = 16; *ty = 16; return 1; }
+  if (tile == TILE_24x8) { *tx = 24; *ty = 8; return 1; }
+  return 0;
+}
+int stage_blocks(int tile, int nx, int ny, int nz, int lz) {
+  int tx, ty;
+  if (!tile_dims(tile, &tx, &ty)) return 0;
+  return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + lz - 1) / lz);
+}
+}  // namespace mhd
+
+extern "C" {
+
+size_t mhd_workspace_bytes(const mhd_params* p) {
+  if (!grid_ok(p)) return 0;
+  if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return 0;
+  return align_up(sizeof(Scalars)) + align_up(sizeof(double) * kDiagBlocks * kDiagVals) +
+         16 * field_bytes(p);
+}
+
+int mhd_create(const mhd_params* p, mhd_ctx** out) {
+  if (!out) return MHD_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!grid_ok(p)) return MHD_ERR_INVALID_ARG;
+  if (!(p->lx > 0) || !(p->ly > 0) || !(p->lz > 0) || !(p->gamma > 1.0) || !(p->cfl > 0.0) ||
+      !(p->cfl < 1.0))
+    return MHD_ERR_INVALID_ARG;
+  if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return MHD_ERR_INVALID_ARG;
+  if (p->riemann != MHD_HLLD && p->riemann != MHD_HLL) return MHD_ERR_INVALID_ARG;
+  if (p->emf != MHD_EMF_EC) return MHD_ERR_UNSUPPORTED;
+  if (p->integrator != MHD_RK2 && p->integrator != MHD_EULER) return MHD_ERR_INVALID_ARG;
+  if (p->zchunk < 0) return MHD_ERR_INVALID_ARG;
+  int tile = p->tile == 0 ? default_tile(p->precision) : p->tile;
+  int tx, ty;
+  if (!tile_dims(tile, &tx, &ty)) return MHD_ERR_INVALID_ARG;
+  if (!p->workspace || ((uintptr_t)p->workspace % kAlign) != 0) return MHD_ERR_WORKSPACE;
+  if (p->workspace_bytes < mhd_workspace_bytes(p)) return MHD_ERR_WORKSPACE;
+
+  mhd_ctx* c = (mhd_ctx*)calloc(1, sizeof(mhd_ctx));
+  if (!c) return MHD_ERR_INVALID_ARG;
+  c->p = *p;
+  c->stream = (hipStream_t)p->stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    free(c);
+    return MHD_ERR_HIP;
+  }
+  c->elem = p->precision == MHD_FP32 ? 4 : 8;
+  c->ncell = (long long)p->nx * p->ny * p->nz;
+  double dx = p->lx / p->nx, dy = p->ly / p->ny, dz = p->lz / p->nz;
+  c->idl[0] = 1.0 / dx;
+  c->idl[1] = 1.0 / dy;
+  c->idl[2] = 1.0 / dz;
+  c->dv = (dx * dy) * dz;
+  char* w = (char*)p->workspace;
+  c->sc = (Scalars*)w;
+  w += align_up(sizeof(Scalars));
+  c->diag_part = (double*)w;
+  w += align_up(sizeof(double) * kDiagBlocks * kDiagVals);
+  const size_t fb = field_bytes(p);
+  for (int b = 0; b < 2; ++b)
+    for (int f = 0; f < 8; ++f) {
+      c->buf[b][f] = w;
+      w += fb;
+    }
+  c->cur = 0;
+  c->tile = tile;
+  c->lz = p->zchunk > 0 ? (p->zchunk < p->nz ? p->zchunk : p->nz) : choose_lz(tile, p->nx, p->ny, p->nz);
+  c->diag_blocks = kDiagBlocks;
+  // raise the dynamic-LDS limit of this tile's kernels (host-side attribute)
+  StageLaunch l = {};
+  l.tile = tile;
+  l.solver = p->riemann;
+  hipError_t e = p->precision == MHD_FP32 ? stage_f32(l, nullptr, true) : stage_f64(l, nullptr, true);
+  if (e != hipSuccess) {
+    free(c);
+    return MHD_ERR_HIP;
+  }
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->stream, c->sc, 0.0, 0.0, p->cfl);
+  if (hipGetLastError() != hipSuccess) {
+    free(c);
+    return MHD_ERR_HIP;
+  }
+  *out = c;
+  return MHD_OK;
+}
+
+int mhd_set_state(mhd_ctx* c, const mhd_state_view* v, double t, double dt_next) {
+  if (!c || !v) return MHD_ERR_INVALID_ARG;
+  void* src[8];
+  fields_of(v, src);
+  for (int f = 0; f < 8; ++f)
+    if (!src[f]) return MHD_ERR_INVALID_ARG;
+  const size_t bytes = (size_t)c->ncell * c->elem;
+  c->cur = 0;
+  for (int f = 0; f < 8; ++f) {
+    hipError_t e = hipMemcpyAsync(c->buf[0][f], src[f], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return MHD_ERR_HIP;
+  }
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->stream, c->sc, t, dt_next, c->p.cfl);
+  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  if (!(dt_next > 0.0)) {
+    // eq. (cfl) on the initial state: the stage kernel in measuring mode
+    hipError_t e = launch_stage(c, 2, 0, 1);
+    if (e != hipSuccess) return MHD_ERR_HIP;
+    hipLaunchKernelGGL(k_init_dt, dim3(1), dim3(1), 0, c->stream, c->sc);
+    if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  }
+  return MHD_OK;
+}
+
+int mhd_step(mhd_ctx* c, int nsteps, double t_stop) {
+  if (!c || nsteps < 0) return MHD_ERR_INVALID_ARG;
+  if (nsteps == 0) return MHD_OK;
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, c->stream, c->sc, t_stop);
+  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  for (int n = 0; n < nsteps; ++n) {
+    const int a = c->cur, b = 1 - c->cur;
+    hipError_t e = launch_stage(c, 0, a, b);  // U_1 = S_dt(U_0), measures dt
+    if (e != hipSuccess) return MHD_ERR_HIP;
+    if (c->p.integrator == MHD_RK2) {
+      e = launch_stage(c, 1, b, a);  // U^{n+1} = 1/2 S_dt(U_1) + 1/2 U_0
+      if (e != hipSuccess) return MHD_ERR_HIP;
+    } else {
+      c->cur = b;
+    }
+    hipLaunchKernelGGL(k_end, dim3(1), dim3(1), 0, c->stream, c->sc, t_stop);
+    if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  }
+  return MHD_OK;
+}
+
+int mhd_get_state(mhd_ctx* c, const mhd_state_view* v, double* t, double* dt_next) {
+  if (!c) return MHD_ERR_INVALID_ARG;
+  if (v) {
+    void* dst[8];
+    fields_of(v, dst);
+    const size_t bytes = (size_t)c->ncell * c->elem;
+    for (int f = 0; f < 8; ++f) {
+      if (!dst[f]) return MHD_ERR_INVALID_ARG;
+      hipError_t e = hipMemcpyAsync(dst[f], c->buf[c->cur][f], bytes, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return MHD_ERR_HIP;
+    }
+  }
+  Scalars h;
+  hipError_t e = hipMemcpyAsync(&h, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return MHD_ERR_HIP;
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return MHD_ERR_HIP;
+  if (t) *t = h.t;
+  if (dt_next) *dt_next = h.dt_next;
+  return h.status ? MHD_ERR_NONPHYSICAL : MHD_OK;
+}
+
+int mhd_get_diagnostics(mhd_ctx* c, mhd_diag* out) {
+  if (!c || !out) return MHD_ERR_INVALID_ARG;
+  void** f = c->buf[c->cur];
+  if (c->p.precision == MHD_FP32) {
+    hipLaunchKernelGGL(k_diag_partial<float>, dim3(c->diag_blocks), dim3(256), 0, c->stream,
+                       (const float*)f[0], (const float*)f[1], (const float*)f[2], (const float*)f[3],
+                       (const float*)f[4], (const float*)f[5], (const float*)f[6], (const float*)f[7],
+                       c->p.nx, c->p.ny, c->p.nz, c->idl[0], c->idl[1], c->idl[2], c->diag_part);
+  } else {
+    hipLaunchKernelGGL(k_diag_partial<double>, dim3(c->diag_blocks), dim3(256), 0, c->stream,
+                       (const double*)f[0], (const double*)f[1], (const double*)f[2],
+                       (const double*)f[3], (const double*)f[4], (const double*)f[5],
+                       (const double*)f[6], (const double*)f[7], c->p.nx, c->p.ny, c->p.nz,
+                       c->idl[0], c->idl[1], c->idl[2], c->diag_part);
+  }
+  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(1), 0, c->stream, c->diag_part, c->diag_blocks,
+                     c->dv, (double)c->ncell, c->sc);
+  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  Scalars h;
+  hipError_t e = hipMemcpyAsync(&h, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return MHD_ERR_HIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return MHD_ERR_HIP;
+  out->mass = h.diag[0];
+  for (int d = 0; d < 3; ++d) out->mom[d] = h.diag[1 + d];
+  out->energy = h.diag[4];
+  for (int d = 0; d < 3; ++d) out->bflux[d] = h.diag[5 + d];
+  out->divb_max = h.diag[8];
+  out->divb_rms = h.diag[9];
+  out->status = h.status;
+  return MHD_OK;
+}
+
+int mhd_step_batch(mhd_ctx* const* ctxs, const int* nsteps, int n, void* stream) {
+  if (!ctxs || !nsteps || n < 0) return MHD_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i] || nsteps[i] < 0) return MHD_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    hipStream_t keep = ctxs[i]->stream;
+    if (stream) ctxs[i]->stream = (hipStream_t)stream;
+    int rc = mhd_step(ctxs[i], nsteps[i], 0.0);
+    ctxs[i]->stream = keep;
+    if (rc) return rc;
+  }
+  return MHD_OK;
+}
+
+int mhd_destroy(mhd_ctx* c) {
+  free(c);
+  return MHD_OK;
+}
+
+const char* mhd_status_string(int code) {
+  switch (code) {
+    case MHD_OK: return "ok";
+    case MHD_ERR_INVALID_ARG: return "invalid argument";
+    case MHD_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case MHD_ERR_HIP: return "HIP runtime error";
+    case MHD_ERR_NONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
+    case MHD_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+// mhd_device.h -- point physics of the ideal-MHD Godunov cycle for gfx950.
+//
+// Lesur et al. 2023 (arXiv:2304.13746): primitive-variable reconstruction with
+// the van Leer limiter (Sec. 2.3), HLL and HLLD Riemann fluxes with pressure in
+// the momentum flux (Sec. 2.3), upwind-by-contact corner EMFs E^c (Sec. 2.4).
+//
+// Every expression is evaluated in the order written (the library is built with
+// -ffp-contract=off, no fast-math), so an FP64 build rounds exactly like a plain
+// left-to-right evaluation of the same formulas.  Maxima and minima use
+// comparisons, not fmax/fmin, so NaN and signed-zero handling is explicit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mhd {
+
+template <typename R>
+struct Tol;
+template <>
+struct Tol<double> {
+  // relative size under which an HLLD star denominator counts as degenerate
+  static constexpr double degen = 1e-12;
+};
+template <>
+struct Tol<float> {
+  static constexpr float degen = 1e-6f;
+};
+
+__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
+
+// van Leer slope: harmonic mean of the one-sided differences if they share a
+// sign, zero otherwise.
+template <typename R>
+__device__ __forceinline__ R van_leer(R dm, R dp) {
+  R s = dp * dm;
+  return s > R(0) ? (R(2) * s) / (dp + dm) : R(0);
+}
+
+// Fast magnetosonic speed from a^2 = gamma p / rho, |B|^2 / rho and B_n^2 / rho.
+template <typename R>
+__device__ __forceinline__ R fast_speed(R gamma, R rho, R p, R bn, R b1, R b2) {
+  R irho = R(1) / rho;
+  R a2 = (gamma * p) * irho;
+  R bb = (bn * bn + b1 * b1) + b2 * b2;
+  R ca2 = bb * irho;
+  R cn2 = (bn * bn) * irho;
+  R s = a2 + ca2;
+  R disc = s * s - R(4) * (a2 * cn2);
+  disc = disc > R(0) ? disc : R(0);
+  return dsqrt(R(0.5) * (s + dsqrt(disc)));
+}
+
+// A face-frame primitive state: (rho, v_n, v_t1, v_t2, B_t1, B_t2, p).
+template <typename R>
+struct Prim {
+  R rho, un, v1, v2, b1, b2, p;
+};
+
+// Conserved vector U = (rho, m_n, m_t1, m_t2, E, B_t1, B_t2), physical flux F and
+// total pressure of one face state with normal field bn.
+template <typename R>
+struct Cons {
+  R u[7];
+  R f[7];
+  R pt;
+};
+
+template <typename R>
+__device__ __forceinline__ void physical(const Prim<R>& w, R bn, R igm1, Cons<R>& c) {
+  R v2sq = (w.un * w.un + w.v1 * w.v1) + w.v2 * w.v2;
+  R bb = (bn * bn + w.b1 * w.b1) + w.b2 * w.b2;
+  R pt = w.p + R(0.5) * bb;
+  R e = (w.p * igm1 + R(0.5) * (w.rho * v2sq)) + R(0.5) * bb;
+  R vb = (w.un * bn + w.v1 * w.b1) + w.v2 * w.b2;
+  R mn = w.rho * w.un;
+  c.u[0] = w.rho;
+  c.u[1] = mn;
+  c.u[2] = w.rho * w.v1;
+  c.u[3] = w.rho * w.v2;
+  c.u[4] = e;
+  c.u[5] = w.b1;
+  c.u[6] = w.b2;
+  c.f[0] = mn;
+  c.f[1] = (mn * w.un + pt) - bn * bn;
+  c.f[2] = mn * w.v1 - bn * w.b1;
+  c.f[3] = mn * w.v2 - bn * w.b2;
+  c.f[4] = (e + pt) * w.un - bn * vb;
+  c.f[5] = w.un * w.b1 - bn * w.v1;
+  c.f[6] = w.un * w.b2 - bn * w.v2;
+  c.pt = pt;
+}
+
+// Outer signal speeds S_L = min(v_n) - max(c_f), S_R = max(v_n) + max(c_f) and the
+// face's largest |speed| for the CFL condition.
+template <typename R>
+__device__ __forceinline__ void outer_speeds(R gamma, const Prim<R>& l, const Prim<R>& r, R bn,
+                                             R& sl, R& sr, R& cmax) {
+  R cfl = fast_speed(gamma, l.rho, l.p, bn, l.b1, l.b2);
+  R cfr = fast_speed(gamma, r.rho, r.p, bn, r.b1, r.b2);
+  R cfm = cfl > cfr ? cfl : cfr;
+  R umin = l.un < r.un ? l.un : r.un;
+  R umax = l.un > r.un ? l.un : r.un;
+  sl = umin - cfm;
+  sr = umax + cfm;
+  R al = dabs(sl), ar = dabs(sr);
+  cmax = al > ar ? al : ar;
+}
+
+// HLL flux (one averaged state between S_L and S_R).
+template <typename R>
+__device__ __forceinline__ void flux_hll(R gamma, R igm1, const Prim<R>& l, const Prim<R>& r, R bn,
+                                         R* f, R& cmax) {
+  Cons<R> cl, cr;
+  physical(l, bn, igm1, cl);
+  physical(r, bn, igm1, cr);
+  R sl, sr;
+  outer_speeds(gamma, l, r, bn, sl, sr, cmax);
+  if (sl >= R(0)) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = cl.f[q];
+  } else if (sr <= R(0)) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = cr.f[q];
+  } else {
+    R ih = R(1) / (sr - sl);
+    R slr = sr * sl;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = ((sr * cl.f[q] - sl * cr.f[q]) + slr * (cr.u[q] - cl.u[q])) * ih;
+  }
+}
+
+// One side of the HLLD single-star region (Miyoshi & Kusano 2005): state behind
+// the fast wave s_a, given the contact speed sm and star total pressure pts.
+template <typename R>
+struct Star {
+  R rho, v1, v2, b1, b2, e, vb;
+};
+
+template <typename R>
+__device__ __forceinline__ void hlld_star(const Prim<R>& w, const Cons<R>& c, R bn, R sa, R sm,
+                                          R pts, Star<R>& st) {
+  R sua = sa - w.un;
+  R da = sua * w.rho;
+  R sam = sa - sm;
+  R isam = R(1) / sam;
+  R rhos = da * isam;
+  R t = da * sam;
+  R bn2 = bn * bn;
+  R den = t - bn2;
+  R v1s, v2s, b1s, b2s;
+  if (dabs(den) <= Tol<R>::degen * (dabs(t) + bn2)) {
+    v1s = w.v1;
+    v2s = w.v2;
+    b1s = w.b1;
+    b2s = w.b2;
+  } else {
+    R iden = R(1) / den;
+    R tv = (bn * (sm - w.un)) * iden;
+    R tb = (da * sua - bn2) * iden;
+    v1s = w.v1 - w.b1 * tv;
+    v2s = w.v2 - w.b2 * tv;
+    b1s = w.b1 * tb;
+    b2s = w.b2 * tb;
+  }
+  R vba = (w.un * bn + w.v1 * w.b1) + w.v2 * w.b2;
+  R vbs = (sm * bn + v1s * b1s) + v2s * b2s;
+  st.e = (((sua * c.u[4] - c.pt * w.un) + pts * sm) + bn * (vba - vbs)) * isam;
+  st.rho = rhos;
+  st.v1 = v1s;
+  st.v2 = v2s;
+  st.b1 = b1s;
+  st.b2 = b2s;
+  st.vb = vbs;
+}
+
+// HLLD flux: fans S_L < S*_L < S_M < S*_R < S_R.
+template <typename R>
+__device__ __forceinline__ void flux_hlld(R gamma, R igm1, const Prim<R>& l, const Prim<R>& r, R bn,
+                                          R* f, R& cmax) {
+  Cons<R> cl, cr;
+  physical(l, bn, igm1, cl);
+  physical(r, bn, igm1, cr);
+  R sl, sr;
+  outer_speeds(gamma, l, r, bn, sl, sr, cmax);
+  if (sl >= R(0)) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = cl.f[q];
+    return;
+  }
+  if (sr <= R(0)) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = cr.f[q];
+    return;
+  }
+  R dl = (sl - l.un) * l.rho;
+  R dr = (sr - r.un) * r.rho;
+  R iden = R(1) / (dr - dl);
+  R sm = (((dr * r.un - dl * l.un) - cr.pt) + cl.pt) * iden;
+  R pts = ((dr * cl.pt - dl * cr.pt) + (dr * dl) * (r.un - l.un)) * iden;
+  Star<R> stl, str;
+  hlld_star(l, cl, bn, sl, sm, pts, stl);
+  hlld_star(r, cr, bn, sr, sm, pts, str);
+  R usl[7] = {stl.rho, stl.rho * sm, stl.rho * stl.v1, stl.rho * stl.v2, stl.e, stl.b1, stl.b2};
+  R usr[7] = {str.rho, str.rho * sm, str.rho * str.v1, str.rho * str.v2, str.e, str.b1, str.b2};
+  R sql = dsqrt(stl.rho), sqr = dsqrt(str.rho);
+  R abn = dabs(bn);
+  R ssl = sm - abn / sql;
+  R ssr = sm + abn / sqr;
+  if (ssl >= R(0)) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = cl.f[q] + sl * (usl[q] - cl.u[q]);
+    return;
+  }
+  if (!(sm >= R(0)) && !(ssr >= R(0))) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = cr.f[q] + sr * (usr[q] - cr.u[q]);
+    return;
+  }
+  R sgn = bn > R(0) ? R(1) : (bn < R(0) ? R(-1) : R(0));
+  R isq = R(1) / (sql + sqr);
+  R v1ss = ((sql * stl.v1 + sqr * str.v1) + (str.b1 - stl.b1) * sgn) * isq;
+  R v2ss = ((sql * stl.v2 + sqr * str.v2) + (str.b2 - stl.b2) * sgn) * isq;
+  R b1ss = ((sql * str.b1 + sqr * stl.b1) + (sql * sqr) * ((str.v1 - stl.v1) * sgn)) * isq;
+  R b2ss = ((sql * str.b2 + sqr * stl.b2) + (sql * sqr) * ((str.v2 - stl.v2) * sgn)) * isq;
+  R vbss = (sm * bn + v1ss * b1ss) + v2ss * b2ss;
+  if (sm >= R(0)) {
+    R ess = stl.e - (sql * (stl.vb - vbss)) * sgn;
+    R uss[7] = {stl.rho, stl.rho * sm, stl.rho * v1ss, stl.rho * v2ss, ess, b1ss, b2ss};
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      R fs = cl.f[q] + sl * (usl[q] - cl.u[q]);
+      f[q] = fs + ssl * (uss[q] - usl[q]);
+    }
+  } else {
+    R ess = str.e + (sqr * (str.vb - vbss)) * sgn;
+    R uss[7] = {str.rho, str.rho * sm, str.rho * v1ss, str.rho * v2ss, ess, b1ss, b2ss};
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      R fs = cr.f[q] + sr * (usr[q] - cr.u[q]);
+      f[q] = fs + ssr * (uss[q] - usr[q]);
+    }
+  }
+}
+
+template <int SOLVER, typename R>
+__device__ __forceinline__ void riemann(R gamma, R igm1, const Prim<R>& l, const Prim<R>& r, R bn,
+                                        R* f, R& cmax) {
+  if constexpr (SOLVER == 1)
+    flux_hll(gamma, igm1, l, r, bn, f, cmax);
+  else
+    flux_hlld(gamma, igm1, l, r, bn, f, cmax);
+}
+
+// Upwind choice by the sign of a mass flux; zero averages the two candidates.
+template <typename R>
+__device__ __forceinline__ R upwind(R s, R l, R r) {
+  return s > R(0) ? l : (s < R(0) ? r : R(0.5) * (l + r));
+}
+
+// E^c corner EMF in the (P, Q) plane at (p-1/2, q-1/2) (Gardiner & Stone 2005):
+// a1, a2 are the P-face EMFs at (p-1/2, q), (p-1/2, q-1); b1, b2 the Q-face EMFs at
+// (p, q-1/2), (p-1, q-1/2); cAB the cell EMFs at (p-1+A, q-1+B); sq1, sq3 the
+// P-face and sp1, sp3 the Q-face mass fluxes next to a1, a2, b1, b2.
+template <typename R>
+__device__ __forceinline__ R corner_emf(R a1, R a2, R b1, R b2, R c00, R c10, R c01, R c11, R sq1,
+                                        R sq3, R sp1, R sp3) {
+  R dq1 = upwind(sq1, c01 - b2, c11 - b1);
+  R dq3 = upwind(sq3, b2 - c00, b1 - c10);
+  R dp1 = upwind(sp1, c10 - a2, c11 - a1);
+  R dp3 = upwind(sp3, a2 - c00, a1 - c01);
+  return R(0.25) * ((((a1 + a2) + (b1 + b2)) + (dq3 - dq1)) + (dp3 - dp1));
+}
+
+}  // namespace mhd

@@ -1,0 +1,71 @@
+// mhd_internal.h -- host/device shared definitions of libmhd (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mhd {
+
+// Per-context device scalars, kept in the workspace so that a cycle never needs
+// the host: the step of the current cycle, the CFL maximum being accumulated
+// (bit pattern of a non-negative double, combined with atomicMax) and the status
+// latch.
+struct Scalars {
+  double t;        // time of the state
+  double dt_next;  // CFL step for the next cycle (eq. cfl)
+  double dt;       // step of the current cycle (dt_next clipped at t_stop)
+  double cfl;      // sigma_CFL
+  unsigned long long invdt_bits;  // running max over cells of sum_d c_max,d / dl_d
+  unsigned status;                // bit 0: non-physical value met
+  unsigned pad;
+  double diag[12];  // diagnostics: mass, mom[3], energy, bflux[3], divb_max, divb_rms
+};
+
+// Device scalars are written by one kernel and read by the next, possibly on
+// another XCD: every such access is an agent-scope atomic, so it never hits a
+// stale cached copy of the line.
+__device__ __forceinline__ double ld_agent(const double* p) {
+  unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double((long long)u);
+}
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_agent(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile variants of the stage kernel.
+enum { TILE_16x16 = 1, TILE_24x8 = 2 };
+
+struct StageLaunch {
+  void* src[8];
+  void* dst[8];
+  int nx, ny, nz;
+  int lz;
+  double idl[3];
+  double gamma;
+  Scalars* sc;
+  int tile, solver, mode;
+};
+
+// stage launch for one precision (mhd_stage_f64.hip / mhd_stage_f32.hip)
+hipError_t stage_f64(const StageLaunch& l, hipStream_t st, bool prepare);
+hipError_t stage_f32(const StageLaunch& l, hipStream_t st, bool prepare);
+int stage_blocks(int tile, int nx, int ny, int nz, int lz);
+int tile_dims(int tile, int* tx, int* ty);
+
+}  // namespace mhd

@@ -1,0 +1,628 @@
+// mhd_stage.hip -- fused stage kernel of the ideal-MHD Godunov cycle (gfx950).
+//
+// One launch applies the stage operator S_dt of Lesur et al. 2023 (Sec. 2.2-2.7,
+// steps S1 primitives, S2 reconstruction, S3 Riemann solves, S5 flux divergence,
+// S7 corner EMFs, S8 constrained-transport update) to a whole periodic box, and
+// either writes U* (first RK2 stage, Euler), writes 1/2 U* + 1/2 U_0 in place
+// over U_0 (second RK2 stage, Tab. weights), or only measures eq. (cfl).
+//
+// Design (2.5D tile, z-march).  A thread block owns a TX x TY column tile of
+// cells and marches one z-chunk.  Each of its TX*TY + 2(TX+TY) threads owns one
+// column of the tile or of the one-cell ring around it and keeps that column's
+// z-window of primitives in registers, so every z-face is solved once by the
+// column that owns it.  Per z-plane the primitives of the plane (with a two-cell
+// halo) go through LDS for the x- and y-reconstructions; x-, y- and z-face
+// results the neighbours need (fluxes, face EMFs, mass fluxes, signal speeds,
+// cell EMFs) are exchanged through LDS; every face is solved once per tile.
+// Fluxes, EMFs and primitives never touch HBM: per cell and stage the kernel
+// reads the 8 state words (halo re-reads hit L2) and writes 8.
+//
+// Index wrap is periodic in every direction; columns of a ragged edge tile that
+// fall outside the box compute as halo (they alias real cells) but write nothing.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mhd_device.h"
+#include "mhd_internal.h"
+
+namespace mhd {
+
+// Arguments of one stage launch.
+template <typename R>
+struct StageArgs {
+  const R* src[8];  // state the operator acts on: rho mx my mz en bx by bz
+  R* dst[8];        // output state (second RK2 stage: also holds U_0)
+  int nx, ny, nz;
+  int ntx, nty, nzc, lz;  // tiles in x, y; z-chunks and their length
+  int nblocks;
+  R idl[3];  // 1 / dl_d
+  R gamma, gm1, igm1;
+  const Scalars* sc;  // device scalars: dt of this cycle, CFL maximum, status
+  Scalars* scw;
+};
+
+enum { MODE_STAGE1 = 0, MODE_STAGE2 = 1, MODE_MEASURE = 2 };
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+template <typename R>
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* bits, R v) {
+  double d = (double)v;  // non-negative doubles order like their bit patterns
+  __hip_atomic_fetch_max(bits, (unsigned long long)__double_as_longlong(d), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Primitive variables of one cell (S1): v = m / rho, cell-centred B is the mean
+// of the two faces, p = (gamma - 1)(E - m.v/2 - B^2/2).
+template <typename R>
+struct Cell {
+  R rho, vx, vy, vz, bx, by, bz, p;
+};
+
+template <typename R>
+__device__ __forceinline__ void to_prim(R rho, R mx, R my, R mz, R en, R bxl, R bxr, R byl, R byr,
+                                        R bzl, R bzr, R gm1, Cell<R>& c) {
+  c.bx = R(0.5) * (bxl + bxr);
+  c.by = R(0.5) * (byl + byr);
+  c.bz = R(0.5) * (bzl + bzr);
+  R irho = R(1) / rho;
+  c.vx = mx * irho;
+  c.vy = my * irho;
+  c.vz = mz * irho;
+  R ke = R(0.5) * ((mx * c.vx + my * c.vy) + mz * c.vz);
+  R me = R(0.5) * ((c.bx * c.bx + c.by * c.by) + c.bz * c.bz);
+  c.p = gm1 * ((en - ke) - me);
+  c.rho = rho;
+}
+
+template <typename R>
+__device__ __forceinline__ bool bad_cell(const Cell<R>& c) {
+  return !(c.rho > R(0)) || !(c.p > R(0)) || !__builtin_isfinite(c.p) ||
+         !__builtin_isfinite(c.vx) || !__builtin_isfinite(c.vy) || !__builtin_isfinite(c.vz) ||
+         !__builtin_isfinite(c.bx) || !__builtin_isfinite(c.by) || !__builtin_isfinite(c.bz);
+}
+
+// Raw loads of one cell for the primitive computation.
+template <typename R>
+struct Raw {
+  R rho, mx, my, mz, en, bxl, bxr, byl, byr, bzl, bzr;
+};
+
+template <typename R>
+__device__ __forceinline__ void load_raw(const StageArgs<R>& a, int gi, int gi1, int gj, int gj1,
+                                         int gk, int gk1, Raw<R>& r) {
+  const long long plane = (long long)a.nx * a.ny;
+  const long long o = (long long)gk * plane + (long long)gj * a.nx + gi;
+  r.rho = a.src[0][o];
+  r.mx = a.src[1][o];
+  r.my = a.src[2][o];
+  r.mz = a.src[3][o];
+  r.en = a.src[4][o];
+  r.bxl = a.src[5][o];
+  r.bxr = a.src[5][o - gi + gi1];
+  r.byl = a.src[6][o];
+  r.byr = a.src[6][o + (long long)(gj1 - gj) * a.nx];
+  r.bzl = a.src[7][o];
+  r.bzr = a.src[7][o + (long long)(gk1 - gk) * plane];
+}
+
+// Face-frame primitive of a cell for direction d (cyclic tangents).
+template <int D, typename R>
+__device__ __forceinline__ void frame_vals(const Cell<R>& c, R* q) {
+  q[0] = c.rho;
+  q[6] = c.p;
+  if constexpr (D == 0) {
+    q[1] = c.vx; q[2] = c.vy; q[3] = c.vz; q[4] = c.by; q[5] = c.bz;
+  } else if constexpr (D == 1) {
+    q[1] = c.vy; q[2] = c.vz; q[3] = c.vx; q[4] = c.bz; q[5] = c.bx;
+  } else {
+    q[1] = c.vz; q[2] = c.vx; q[3] = c.vy; q[4] = c.bx; q[5] = c.by;
+  }
+}
+
+// Grid-frame conserved flux (rho, mx, my, mz, E) from a face-frame flux.
+template <int D, typename R>
+__device__ __forceinline__ void to_grid(const R* f, R* g) {
+  g[0] = f[0];
+  g[4] = f[4];
+  if constexpr (D == 0) {
+    g[1] = f[1]; g[2] = f[2]; g[3] = f[3];
+  } else if constexpr (D == 1) {
+    g[1] = f[3]; g[2] = f[1]; g[3] = f[2];
+  } else {
+    g[1] = f[2]; g[2] = f[3]; g[3] = f[1];
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ Prim<R> as_prim(const R* q) {
+  Prim<R> w;
+  w.rho = q[0]; w.un = q[1]; w.v1 = q[2]; w.v2 = q[3]; w.b1 = q[4]; w.b2 = q[5]; w.p = q[6];
+  return w;
+}
+
+// Per-face result kept by the owning thread.
+template <typename R>
+struct Face {
+  R cons[5];  // grid-frame flux of rho, mx, my, mz, E
+  R fb1, fb2; // face-frame fluxes of B_t1, B_t2
+  R cmax;
+};
+
+template <int D, int SOLVER, typename R>
+__device__ __forceinline__ void solve_face(const StageArgs<R>& a, const R* ql, const R* qr, R bn,
+                                           Face<R>& out) {
+  R f[7];
+  riemann<SOLVER>(a.gamma, a.igm1, as_prim(ql), as_prim(qr), bn, f, out.cmax);
+  to_grid<D>(f, out.cons);
+  out.fb1 = f[5];
+  out.fb2 = f[6];
+}
+
+// Tile geometry: TX x TY interior, threads own interior columns then the ring.
+template <int TX, int TY>
+struct Tile {
+  static constexpr int NT = TX * TY + 2 * (TX + TY);  // threads per block
+  static constexpr int EP = TX + 2, EQ = TY + 2;      // extended column grid
+  static constexpr int NE = EP * EQ;
+  static constexpr int WP = TX + 4, WQ = TY + 4;      // primitive plane with 2-halo
+  static constexpr int NW = WP * WQ;
+  static constexpr int NX_EXTRA = 2 * (TX + TY) + 10;  // halo primitives no thread owns
+  __device__ static void column(int t, int& ci, int& cj) {
+    if (t < TX * TY) {
+      ci = t % TX;
+      cj = t / TX;
+      return;
+    }
+    int r = t - TX * TY;
+    if (r < TY) { ci = -1; cj = r; return; }
+    r -= TY;
+    if (r < TY) { ci = TX; cj = r; return; }
+    r -= TY;
+    if (r < TX) { ci = r; cj = -1; return; }
+    r -= TX;
+    ci = r; cj = TY;
+  }
+  // halo primitive items: second ring and the four corners of the first ring
+  __device__ static void extra(int t, int& ci, int& cj) {
+    int r = t;
+    if (r < TY + 2) { ci = -2; cj = r - 1; return; }
+    r -= TY + 2;
+    if (r < TY + 1) { ci = TX + 1; cj = r - 1; return; }
+    r -= TY + 1;
+    if (r < TX + 2) { ci = r - 1; cj = -2; return; }
+    r -= TX + 2;
+    if (r < TX + 1) { ci = r - 1; cj = TY + 1; return; }
+    r -= TX + 1;
+    ci = (r & 1) ? TX : -1;
+    cj = (r & 2) ? TY : -1;
+  }
+  __device__ static int e(int ci, int cj) { return (cj + 1) * EP + (ci + 1); }
+  __device__ static int w(int ci, int cj) { return (cj + 2) * WP + (ci + 2); }
+};
+
+// LDS layout (units of R): primitive plane, per-column exports, corner EMFs.
+template <typename R, int TX, int TY>
+struct Smem {
+  using T = Tile<TX, TY>;
+  R w[8][T::NW];
+  R xcons[5][T::NE], xez[T::NE], xmass[T::NE], xcmax[T::NE];
+  R ycons[5][T::NE], yez[T::NE], ymass[T::NE], ycmax[T::NE];
+  R zex[T::NE], zey[T::NE], zmass[T::NE];
+  R erz[T::NE], erx[T::NE], erxp[T::NE], ery[T::NE], eryp[T::NE];
+  R ez[T::NE], ex[T::NE], ey[T::NE];
+};
+
+template <typename R, int SOLVER, int MODE, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY + 2 * (TX + TY))
+stage_kernel(StageArgs<R> a) {
+  using T = Tile<TX, TY>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Smem<R, TX, TY>& S = *reinterpret_cast<Smem<R, TX, TY>*>(smem_raw);
+
+  // XCD-aware order: the hardware deals blocks round-robin over 8 XCDs; give
+  // each XCD a contiguous run of spatially adjacent tiles so halos hit its L2.
+  int b = blockIdx.x;
+  {
+    const int q = a.nblocks / 8, rr = a.nblocks % 8;
+    const int x = b % 8, s = b / 8;
+    b = (x < rr ? x * (q + 1) : rr * (q + 1) + (x - rr) * q) + s;
+  }
+  const int tx = b % a.ntx;
+  const int ty = (b / a.ntx) % a.nty;
+  const int tz = b / (a.ntx * a.nty);
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int z0 = tz * a.lz;
+  const int z1 = min(z0 + a.lz, a.nz);
+
+  const int t = threadIdx.x;
+  int ci, cj;
+  T::column(t, ci, cj);
+  const int gi = wrapi(x0 + ci, a.nx), gj = wrapi(y0 + cj, a.ny);
+  const int gi1 = wrapi(gi + 1, a.nx), gj1 = wrapi(gj + 1, a.ny);
+  const bool interior = ci >= 0 && ci < TX && cj >= 0 && cj < TY;
+  const bool real = interior && (x0 + ci < a.nx) && (y0 + cj < a.ny);
+  const bool left = ci == -1, right = ci == TX, bottom = cj == -1, top = cj == TY;
+  const bool do_x = !left;                   // own x-face (ci-1/2, cj)
+  const bool do_y = !bottom;                 // own y-face (ci, cj-1/2)
+  const bool do_ez = !left && !bottom;       // E_z at (ci-1/2, cj-1/2)
+  const bool do_ex = interior || top;        // E_x at (ci, cj-1/2)
+  const bool do_ey = interior || right;      // E_y at (ci-1/2, cj)
+  // corner faces: the first left-ring thread solves x-face (TX, -1), the first
+  // bottom-ring thread y-face (-1, TY)
+  const bool corner_x = (t == TX * TY);
+  const bool corner_y = (t == TX * TY + 2 * TY);
+  const int ex_me = T::e(ci, cj);
+
+  // halo primitive item of this thread (if any)
+  const bool has_extra = t < T::NX_EXTRA;
+  int xci = 0, xcj = 0;
+  if (has_extra) T::extra(t, xci, xcj);
+  const int xgi = wrapi(x0 + xci, a.nx), xgj = wrapi(y0 + xcj, a.ny);
+  const int xgi1 = wrapi(xgi + 1, a.nx), xgj1 = wrapi(xgj + 1, a.ny);
+  const bool extra_corner = has_extra && xci >= -1 && xci <= TX && xcj >= -1 && xcj <= TY;
+
+  const double dtd = ld_agent(&a.sc->dt);
+  const R dt = (R)dtd;
+  const R tau_x = dt * a.idl[0], tau_y = dt * a.idl[1], tau_z = dt * a.idl[2];
+
+  // ---- registers carried along the march
+  Cell<R> wm1, w0;     // primitives of planes m-1 and m (own column)
+  R top7[7];           // z-face left state from the top of cell m-1
+  R bx_m = 0, by_m = 0, bz_m = 0;     // face B of plane m (own column)
+  R bx_p = 0, by_p = 0;                // face B of plane m-1
+  R u_m[5] = {0, 0, 0, 0, 0};          // conserved of plane m (own column)
+  R part[5] = {0, 0, 0, 0, 0};         // U - tau_x dFx - tau_y dFy of cell m-1
+  R fz_prev[5] = {0, 0, 0, 0, 0};      // z-flux at (m-1)-1/2
+  R zc_prev = 0;                       // its signal speed
+  R cxy_prev = 0;                      // x,y part of inv_dt of cell m-1
+  R xey_prev = 0, xmass_prev = 0;      // own x-face E_y part and mass flux, plane m-1
+  R yex_prev = 0, ymass_prev = 0;      // own y-face E_x part and mass flux, plane m-1
+  R erx_prev = 0, ery_prev = 0;        // own cell EMFs of plane m-1
+  R ex_prev = 0, ey_prev = 0;          // own E_x, E_y at (m-1)-1/2
+  R erz_extra = 0;                     // corner cell E_z of plane m (halo item)
+  R inv_max = 0;
+  bool bad = false;
+
+  // ---- prologue: primitives of planes z0-2 and z0-1
+  {
+    Raw<R> r;
+    int k = wrapi(z0 - 2, a.nz);
+    load_raw(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
+    to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, wm1);
+    k = wrapi(z0 - 1, a.nz);
+    load_raw(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
+    to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w0);
+    bx_m = r.bxl; by_m = r.byl; bz_m = r.bzl;
+    u_m[0] = r.rho; u_m[1] = r.mx; u_m[2] = r.my; u_m[3] = r.mz; u_m[4] = r.en;
+    const int iw = T::w(ci, cj);
+    S.w[0][iw] = w0.rho; S.w[1][iw] = w0.vx; S.w[2][iw] = w0.vy; S.w[3][iw] = w0.vz;
+    S.w[4][iw] = w0.bx; S.w[5][iw] = w0.by; S.w[6][iw] = w0.bz; S.w[7][iw] = w0.p;
+    if (has_extra) {
+      Cell<R> c;
+      load_raw(a, xgi, xgi1, xgj, xgj1, k, wrapi(k + 1, a.nz), r);
+      to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, c);
+      const int jw = T::w(xci, xcj);
+      S.w[0][jw] = c.rho; S.w[1][jw] = c.vx; S.w[2][jw] = c.vy; S.w[3][jw] = c.vz;
+      S.w[4][jw] = c.bx; S.w[5][jw] = c.by; S.w[6][jw] = c.bz; S.w[7][jw] = c.p;
+      erz_extra = c.vy * c.bx - c.vx * c.by;
+    }
+    for (int v = 0; v < 7; ++v) top7[v] = 0;
+  }
+  __syncthreads();
+
+  for (int m = z0 - 1; m <= z1; ++m) {
+    const int km = wrapi(m, a.nz);
+    // ---------------- A: x- and y-faces of plane m from the LDS plane
+    Face<R> fx = {}, fy = {};
+    if (do_x || corner_x) {
+      const int fi = corner_x ? TX : ci, fj = corner_x ? -1 : cj;
+      R q[4][7];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        Cell<R> c;
+        const int iw = T::w(fi - 2 + s, fj);
+        c.rho = S.w[0][iw]; c.vx = S.w[1][iw]; c.vy = S.w[2][iw]; c.vz = S.w[3][iw];
+        c.bx = S.w[4][iw]; c.by = S.w[5][iw]; c.bz = S.w[6][iw]; c.p = S.w[7][iw];
+        frame_vals<0>(c, q[s]);
+      }
+      R ql[7], qr[7];
+#pragma unroll
+      for (int v = 0; v < 7; ++v) {
+        R sl = van_leer(q[1][v] - q[0][v], q[2][v] - q[1][v]);
+        R sr = van_leer(q[2][v] - q[1][v], q[3][v] - q[2][v]);
+        ql[v] = q[1][v] + R(0.5) * sl;
+        qr[v] = q[2][v] - R(0.5) * sr;
+      }
+      R bn;
+      if (corner_x) {
+        const long long o = (long long)km * a.nx * a.ny + (long long)wrapi(y0 - 1, a.ny) * a.nx +
+                            wrapi(x0 + TX, a.nx);
+        bn = a.src[5][o];
+      } else {
+        bn = bx_m;
+      }
+      solve_face<0, SOLVER>(a, ql, qr, bn, fx);
+      // the previous plane's exports were consumed before the last barrier
+      if (corner_x) {
+        const int ec = T::e(TX, -1);
+        S.xez[ec] = -fx.fb1;
+        S.xmass[ec] = fx.cons[0];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) S.xcons[q][ex_me] = fx.cons[q];
+        S.xez[ex_me] = -fx.fb1;
+        S.xmass[ex_me] = fx.cons[0];
+        S.xcmax[ex_me] = fx.cmax;
+      }
+    }
+    if (do_y || corner_y) {
+      const int fi = corner_y ? -1 : ci, fj = corner_y ? TY : cj;
+      R q[4][7];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        Cell<R> c;
+        const int iw = T::w(fi, fj - 2 + s);
+        c.rho = S.w[0][iw]; c.vx = S.w[1][iw]; c.vy = S.w[2][iw]; c.vz = S.w[3][iw];
+        c.bx = S.w[4][iw]; c.by = S.w[5][iw]; c.bz = S.w[6][iw]; c.p = S.w[7][iw];
+        frame_vals<1>(c, q[s]);
+      }
+      R ql[7], qr[7];
+#pragma unroll
+      for (int v = 0; v < 7; ++v) {
+        R sl = van_leer(q[1][v] - q[0][v], q[2][v] - q[1][v]);
+        R sr = van_leer(q[2][v] - q[1][v], q[3][v] - q[2][v]);
+        ql[v] = q[1][v] + R(0.5) * sl;
+        qr[v] = q[2][v] - R(0.5) * sr;
+      }
+      R bn;
+      if (corner_y) {
+        const long long o = (long long)km * a.nx * a.ny + (long long)wrapi(y0 + TY, a.ny) * a.nx +
+                            wrapi(x0 - 1, a.nx);
+        bn = a.src[6][o];
+      } else {
+        bn = by_m;
+      }
+      solve_face<1, SOLVER>(a, ql, qr, bn, fy);
+      if (corner_y) {
+        const int ec = T::e(-1, TY);
+        S.yez[ec] = fy.fb2;
+        S.ymass[ec] = fy.cons[0];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) S.ycons[q][ex_me] = fy.cons[q];
+        S.yez[ex_me] = fy.fb2;
+        S.ymass[ex_me] = fy.cons[0];
+        S.ycmax[ex_me] = fy.cmax;
+      }
+    }
+    // own face values needed after the barrier
+    const R xey_now = fx.fb2, xmass_now = fx.cons[0];
+    const R yex_now = -fy.fb1, ymass_now = fy.cons[0];
+
+    // ---------------- next plane's primitives and the z-face at m-1/2
+    Cell<R> w1;
+    R bx_n, by_n, bz_n, u_n[5];
+    {
+      Raw<R> r;
+      const int kn = wrapi(m + 1, a.nz);
+      load_raw(a, gi, gi1, gj, gj1, kn, wrapi(kn + 1, a.nz), r);
+      to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w1);
+      bx_n = r.bxl; by_n = r.byl; bz_n = r.bzl;
+      u_n[0] = r.rho; u_n[1] = r.mx; u_n[2] = r.my; u_n[3] = r.mz; u_n[4] = r.en;
+    }
+    Cell<R> wx;  // halo item of plane m+1
+    if (has_extra) {
+      Raw<R> r;
+      const int kn = wrapi(m + 1, a.nz);
+      load_raw(a, xgi, xgi1, xgj, xgj1, kn, wrapi(kn + 1, a.nz), r);
+      to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, wx);
+    }
+    Face<R> fz = {};
+    {
+      R qa[7], qb[7], qc[7];
+      frame_vals<2>(wm1, qa);
+      frame_vals<2>(w0, qb);
+      frame_vals<2>(w1, qc);
+      R bot[7];
+#pragma unroll
+      for (int v = 0; v < 7; ++v) {
+        R s = van_leer(qb[v] - qa[v], qc[v] - qb[v]);
+        bot[v] = qb[v] - R(0.5) * s;
+        qa[v] = qb[v] + R(0.5) * s;  // becomes top of cell m
+      }
+      if (m >= z0) solve_face<2, SOLVER>(a, top7, bot, bz_m, fz);
+#pragma unroll
+      for (int v = 0; v < 7; ++v) top7[v] = qa[v];
+    }
+    // own cell EMFs of plane m: -(v x B)
+    const R erx = w0.vz * w0.by - w0.vy * w0.bz;
+    const R ery = w0.vx * w0.bz - w0.vz * w0.bx;
+    const R erz = w0.vy * w0.bx - w0.vx * w0.by;
+    if (real && m >= z0 && m < z1) bad |= bad_cell(w0);
+
+    S.zex[ex_me] = fz.fb2;
+    S.zey[ex_me] = -fz.fb1;
+    S.zmass[ex_me] = fz.cons[0];
+    S.erz[ex_me] = erz;
+    S.erx[ex_me] = erx;
+    S.erxp[ex_me] = erx_prev;
+    S.ery[ex_me] = ery;
+    S.eryp[ex_me] = ery_prev;
+    if (extra_corner) S.erz[T::e(xci, xcj)] = erz_extra;
+    __syncthreads();  // plane-m primitives no longer read
+    // ---------------- B: the next primitive plane
+    {
+      const int iw = T::w(ci, cj);
+      S.w[0][iw] = w1.rho; S.w[1][iw] = w1.vx; S.w[2][iw] = w1.vy; S.w[3][iw] = w1.vz;
+      S.w[4][iw] = w1.bx; S.w[5][iw] = w1.by; S.w[6][iw] = w1.bz; S.w[7][iw] = w1.p;
+    }
+    if (has_extra) {
+      const int jw = T::w(xci, xcj);
+      S.w[0][jw] = wx.rho; S.w[1][jw] = wx.vx; S.w[2][jw] = wx.vy; S.w[3][jw] = wx.vz;
+      S.w[4][jw] = wx.bx; S.w[5][jw] = wx.by; S.w[6][jw] = wx.bz; S.w[7][jw] = wx.p;
+    }
+    __syncthreads();
+
+    // ---------------- C: corner EMFs, cell update of plane m-1
+    R ez_new = 0, ex_new = 0, ey_new = 0;
+    if (do_ez && m >= z0 && m < z1) {
+      const int e_s = T::e(ci, cj - 1), e_w = T::e(ci - 1, cj), e_sw = T::e(ci - 1, cj - 1);
+      ez_new = corner_emf(S.xez[ex_me], S.xez[e_s], S.yez[ex_me], S.yez[e_w], S.erz[e_sw],
+                          S.erz[e_s], S.erz[e_w], S.erz[ex_me], S.xmass[ex_me], S.xmass[e_s],
+                          S.ymass[ex_me], S.ymass[e_w]);
+    }
+    if (m >= z0) {
+      if (do_ex) {
+        const int e_s = T::e(ci, cj - 1);
+        ex_new = corner_emf(yex_now, yex_prev, fz.fb2, S.zex[e_s], S.erxp[e_s], erx_prev,
+                            S.erx[e_s], erx, ymass_now, ymass_prev, fz.cons[0], S.zmass[e_s]);
+      }
+      if (do_ey) {
+        const int e_w = T::e(ci - 1, cj);
+        ey_new = corner_emf(-fz.fb1, S.zey[e_w], xey_now, xey_prev, S.eryp[e_w], S.ery[e_w], ery_prev,
+                            ery, fz.cons[0], S.zmass[e_w], xmass_now, xmass_prev);
+      }
+    }
+    // partial update of cell m (x then y), kept for the next iteration
+    R part_new[5];
+    R cxy_new = 0;
+    if (interior && m >= z0 && m < z1) {
+      const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+        part_new[q] = (u_m[q] - tau_x * (S.xcons[q][e_e] - S.xcons[q][ex_me])) -
+                      tau_y * (S.ycons[q][e_n] - S.ycons[q][ex_me]);
+      if constexpr (MODE != MODE_STAGE2) {
+        R cx = S.xcmax[ex_me] > S.xcmax[e_e] ? S.xcmax[ex_me] : S.xcmax[e_e];
+        R cy = S.ycmax[ex_me] > S.ycmax[e_n] ? S.ycmax[ex_me] : S.ycmax[e_n];
+        cxy_new = cx * a.idl[0] + cy * a.idl[1];
+      }
+    }
+    // finalise cell m-1: z-flux difference, stage combination, face B
+    const long long plane = (long long)a.nx * a.ny;
+    if (real && m - 1 >= z0 && m <= z1) {
+      const long long o = (long long)wrapi(m - 1, a.nz) * plane + (long long)gj * a.nx + gi;
+      if constexpr (MODE != MODE_STAGE2) {
+        R cz = zc_prev > fz.cmax ? zc_prev : fz.cmax;
+        R inv = cxy_prev + cz * a.idl[2];
+        inv_max = inv > inv_max ? inv : inv_max;
+      }
+      if constexpr (MODE != MODE_MEASURE) {
+        R un[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) un[q] = part[q] - tau_z * (fz.cons[q] - fz_prev[q]);
+        const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
+        R bxn = (bx_p - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
+        R byn = (by_p - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
+        if constexpr (MODE == MODE_STAGE2) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) un[q] = R(0.5) * un[q] + R(0.5) * a.dst[q][o];
+          bxn = R(0.5) * bxn + R(0.5) * a.dst[5][o];
+          byn = R(0.5) * byn + R(0.5) * a.dst[6][o];
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) a.dst[q][o] = un[q];
+        a.dst[5][o] = bxn;
+        a.dst[6][o] = byn;
+      }
+    }
+    __syncthreads();  // reads of corner-EMF buffers of plane m-1 done
+
+    // ---------------- D: publish corner EMFs; E: B_z on face m-1/2
+    if (do_ez) S.ez[ex_me] = ez_new;
+    if (do_ex) S.ex[ex_me] = ex_new;
+    if (do_ey) S.ey[ex_me] = ey_new;
+    __syncthreads();
+    if constexpr (MODE != MODE_MEASURE) {
+      if (real && m >= z0 && m < z1) {
+        const long long o = (long long)km * plane + (long long)gj * a.nx + gi;
+        const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
+        R bzn = (bz_m - tau_x * (S.ey[e_e] - ey_new)) + tau_y * (S.ex[e_n] - ex_new);
+        if constexpr (MODE == MODE_STAGE2) bzn = R(0.5) * bzn + R(0.5) * a.dst[7][o];
+        a.dst[7][o] = bzn;
+      }
+    }
+
+    // ---------------- shift the march registers
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      part[q] = part_new[q];
+      fz_prev[q] = fz.cons[q];
+      u_m[q] = u_n[q];
+    }
+    zc_prev = fz.cmax;
+    cxy_prev = cxy_new;
+    xey_prev = xey_now;
+    xmass_prev = xmass_now;
+    yex_prev = yex_now;
+    ymass_prev = ymass_now;
+    erx_prev = erx;
+    ery_prev = ery;
+    ex_prev = ex_new;
+    ey_prev = ey_new;
+    bx_p = bx_m; by_p = by_m;
+    bx_m = bx_n; by_m = by_n; bz_m = bz_n;
+    wm1 = w0;
+    w0 = w1;
+    if (extra_corner) erz_extra = wx.vy * wx.bx - wx.vx * wx.by;
+    // the LDS plane now holds plane m+1 (written in B)
+  }
+
+  // ---- block results: CFL maximum and status
+  if constexpr (MODE != MODE_STAGE2) {
+    R v = inv_max;
+    for (int off = 32; off > 0; off >>= 1) {
+      R o = __shfl_xor(v, off);
+      v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomic_max_pos(&a.scw->invdt_bits, v);
+  }
+  if (__any(bad)) {
+    if ((threadIdx.x & 63) == 0)
+      __hip_atomic_fetch_or(&a.scw->status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+
+// Launch one instantiation.  With prepare = true only raise its dynamic-LDS
+// limit (a host-side attribute, done once when a context is created).
+template <typename R, int SOLVER, int MODE, int TX, int TY>
+static hipError_t launch_one(const StageArgs<R>& a, hipStream_t st, bool prepare) {
+  using T = Tile<TX, TY>;
+  const size_t lds = sizeof(Smem<R, TX, TY>);
+  auto fn = stage_kernel<R, SOLVER, MODE, TX, TY>;
+  if (prepare)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(fn, dim3(a.nblocks), dim3(T::NT), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename R, int TX, int TY>
+static hipError_t launch_tile(const StageArgs<R>& a, int solver, int mode, hipStream_t st,
+                              bool prepare) {
+  if (solver == 0) {
+    if (mode == MODE_STAGE1) return launch_one<R, 0, MODE_STAGE1, TX, TY>(a, st, prepare);
+    if (mode == MODE_STAGE2) return launch_one<R, 0, MODE_STAGE2, TX, TY>(a, st, prepare);
+    return launch_one<R, 0, MODE_MEASURE, TX, TY>(a, st, prepare);
+  }
+  if (mode == MODE_STAGE1) return launch_one<R, 1, MODE_STAGE1, TX, TY>(a, st, prepare);
+  if (mode == MODE_STAGE2) return launch_one<R, 1, MODE_STAGE2, TX, TY>(a, st, prepare);
+  return launch_one<R, 1, MODE_MEASURE, TX, TY>(a, st, prepare);
+}
+
+template <typename R, int TX, int TY>
+static hipError_t prepare_tile(int solver) {
+  StageArgs<R> a = {};
+  for (int mode = 0; mode < 3; ++mode) {
+    hipError_t e = launch_tile<R, TX, TY>(a, solver, mode, nullptr, true);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace mhd

@@ -1,0 +1,115 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle.
+
+Tolerances: FP64 runs must agree to 1e-12 norm-wise relative (and are expected
+to be bit-identical: both sides evaluate the same expressions in the same order
+without fused multiply-add); FP32 runs, started from FP32-rounded inputs, to
+1e-5 norm-wise relative against the FP64 oracle on those inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import FIELDS, bit_equal, max_rel, need_gpu, run_both
+from paper_2304_13746_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+def test_orszag_tang_32_fp64_bit_exact(riemann):
+    """Orszag-Tang 32^3 (gamma 5/3, CFL 0.3, seeded rho noise), 10 RK2 cycles:
+    state and the dt sequence agree with the oracle bit for bit."""
+    need_gpu()
+    s = I.orszag_tang(32)
+    g, o, gd, od, (tg, to) = run_both(s, (32, 32, 32), 10, riemann=riemann, per_step=True)
+    print("max rel diff", max_rel(g, o), "bit-equal", bit_equal(g, o))
+    assert max_rel(g, o) <= 1e-12
+    assert gd == od, (gd, od)
+    assert tg == to
+    assert bit_equal(g, o)
+
+
+@pytest.mark.parametrize("dims", [(48, 20, 7), (24, 40, 33), (16, 16, 16), (40, 8, 24)])
+def test_ragged_boxes_fp64(dims):
+    """Boxes that are not multiples of the tile, with several tiles and z-chunks,
+    non-cubic cells: bit-identical to the oracle after 4 cycles."""
+    need_gpu()
+    nx, ny, nz = dims
+    h = 1.0 / max(dims)
+    s = I.turbulence(dims, seed=7, kpeak=2.0, mach=0.8, b0=(0.3, -0.2, 0.1))
+    l = s.pop("_l")
+    l = (nx * h * 1.0, ny * h * 1.3, nz * h * 0.8)
+    g, o, gd, od, _ = run_both(s, dims, 4, l=l, zchunk=5)
+    print(dims, "max rel diff", max_rel(g, o))
+    assert max_rel(g, o) <= 1e-12
+    assert gd == od
+    assert bit_equal(g, o)
+
+
+def test_one_dimensional_boxes_fp64():
+    """Degenerate extents (n = 1 in two directions): the Sod double tube along x,
+    and the same problem along z."""
+    need_gpu()
+    for axis in (0, 2):
+        n = 64
+        s = I.shock_tube_1d(n, {"rho": 1.0, "v": (0, 0, 0), "p": 1.0, "B": (0.5, 1.0, 0.0)},
+                            {"rho": 0.125, "v": (0, 0, 0), "p": 0.1, "B": (0.5, -1.0, 0.0)},
+                            5.0 / 3.0, axis=axis)
+        dims = [1, 1, 1]
+        dims[axis] = n
+        l = [1.0 / n] * 3
+        l[axis] = 1.0
+        g, o, gd, od, _ = run_both(s, tuple(dims), 20, l=tuple(l))
+        assert max_rel(g, o) <= 1e-12
+        assert bit_equal(g, o)
+
+
+def test_euler_integrator_fp64():
+    need_gpu()
+    s = I.orszag_tang(16)
+    g, o, gd, od, _ = run_both(s, (16, 16, 16), 5, integrator="euler")
+    assert max_rel(g, o) <= 1e-12
+    assert bit_equal(g, o)
+
+
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+def test_orszag_tang_32_fp32(riemann):
+    """FP32 state and arithmetic vs the FP64 oracle from the same FP32-rounded
+    input: 1e-5 norm-wise relative after 10 cycles."""
+    need_gpu()
+    s = I.to_float32_exact(I.orszag_tang(32))
+    g, o, gd, od, _ = run_both(s, (32, 32, 32), 10, riemann=riemann, precision="fp32")
+    err = max_rel(g, o)
+    print("fp32 max rel diff", err)
+    assert err <= 1e-5
+    assert abs(gd[-1] - od[-1]) <= 1e-5 * od[-1]
+
+
+def test_uniform_state_bit_invariant_gpu():
+    need_gpu()
+    s = I.assemble(1.2, 0.3, -0.4, 0.2, 0.7, 0.3, 0.2, -0.5, 5.0 / 3.0, shape=(20, 18, 36))
+    for prec in ("fp64", "fp32"):
+        g, o, gd, od, _ = run_both(s, (36, 18, 20), 3, precision=prec)
+        for f in FIELDS:
+            want = s[f].astype(np.float32).astype(np.float64) if prec == "fp32" else s[f]
+            assert np.array_equal(g[f], want), (prec, f)
+
+
+def test_linear_wave_gpu_matches_oracle():
+    """The inclined linear Alfven wave (Sec. 4.2) for one crossing time with the
+    t_stop clip: bit-identical to the oracle, and t lands on t_stop."""
+    need_gpu()
+    from helpers import run_to
+    s, info = I.linear_wave("alfven", 16)
+    dims = info["dims"]
+    tc = 1.0 / info["speed"]
+    from paper_2304_13746_amd.box import MHDBox
+    box = MHDBox(*dims, *info["l"])
+    box.set_state(s)
+    o = O.copy_state(s)
+    p = O.Params(*dims, *info["l"])
+    _, ncyc = run_to(p, o, tc)
+    box.step(ncyc, t_stop=tc)
+    g, tg, _, _ = box.get_state_numpy()
+    assert tg == pytest.approx(tc, rel=1e-14)
+    assert bit_equal(g, o)
