@@ -78,6 +78,7 @@ def lib():
         L.orc_phys_flux.argtypes = [C.c_double, dp, C.c_double, dp, dp]
         L.orc_corner_emf.argtypes = [C.c_double] * 12
         L.orc_corner_emf.restype = C.c_double
+        L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -181,3 +182,7 @@ def phys_flux(gamma: float, w, bn: float):
 
 def corner_emf(a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3) -> float:
     return lib().orc_corner_emf(a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())

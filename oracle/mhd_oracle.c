@@ -34,6 +34,7 @@
 #include "mhd_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -714,3 +715,5 @@ int orc_diagnostics(const orc_params* p, const orc_state* s, double out[10]) {
   out[9] = sqrt((d2.s + d2.c) / (double)g.n);
   return ORC_OK;
 }
+
+int orc_num_threads(void) { return omp_get_max_threads(); }

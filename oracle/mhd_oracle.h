@@ -58,6 +58,9 @@ int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next,
  * out[9] rms div B. */
 int orc_diagnostics(const orc_params* p, const orc_state* s, double out[10]);
 
+/* Threads the OpenMP loops use (the CPU-baseline report states it). */
+int orc_num_threads(void);
+
 /* ---- single building blocks, exported so tests can pin them ---- */
 
 /* van Leer limited slope from the backward and forward differences. */

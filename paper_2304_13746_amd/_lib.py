@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmhd.so")
+# MHD_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("MHD_LIB") or os.path.join(HERE, "libmhd.so")
 
 MHD_OK = 0
 MHD_ERR_INVALID_ARG = -1

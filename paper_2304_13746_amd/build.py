@@ -17,33 +17,40 @@ LIB = os.path.join(HERE, "libmhd.so")
 SOURCES = ["mhd_api.hip", "mhd_stage_f64.hip", "mhd_stage_f32.hip"]
 ARCH = os.environ.get("MHD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", f"--offload-arch={ARCH}", "-ffp-contract=off", "-fPIC", "-std=c++17",
+FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
          "-Wno-unused-variable", "-Wno-unused-function"]
+# FP64 (and the host-side API) round exactly as written, like the CPU reference;
+# the FP32 kernels, checked against a tolerance, may fuse multiply-adds.
+CONTRACT = {"mhd_stage_f32.hip": "-ffp-contract=fast"}
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, "-c", *FLAGS, os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, defines=(), tag: str = "") -> str:
+    obj = os.path.join(BUILD, src.replace(".hip", f"{tag}.o"))
+    cmd = [HIPCC, "-c", *FLAGS, CONTRACT.get(src, "-ffp-contract=off"), *defines,
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile and link libmhd.so; ``defines`` (-D...) build a tuning variant
+    into ``out``."""
     os.makedirs(BUILD, exist_ok=True)
+    tag = "" if out == LIB else "_" + os.path.basename(out).replace(".so", "")
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, defines, tag), SOURCES))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

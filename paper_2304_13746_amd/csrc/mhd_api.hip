@@ -39,7 +39,7 @@ bool grid_ok(const mhd_params* p) {
          p->nz <= 4096;
 }
 
-int default_tile(int precision) { return precision == MHD_FP32 ? TILE_16x16 : TILE_16x16; }
+int default_tile(int precision) { return precision == MHD_FP32 ? TILE_24x8 : TILE_24x8; }
 
 size_t field_bytes(const mhd_params* p) {
   size_t e = p->precision == MHD_FP32 ? 4 : 8;

@@ -26,8 +26,15 @@ struct Tol<float> {
   static constexpr float degen = 1e-6f;
 };
 
+// FP64 keeps IEEE division and square root (correctly rounded, as on the host).
+// FP32 uses the hardware reciprocal and square root (about 1 ulp), whose
+// error is far below the FP32 state's own rounding over a run.
 __device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double dvd(double a, double b) { return a / b; }
+__device__ __forceinline__ float dvd(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
 
@@ -36,13 +43,13 @@ __device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
 template <typename R>
 __device__ __forceinline__ R van_leer(R dm, R dp) {
   R s = dp * dm;
-  return s > R(0) ? (R(2) * s) / (dp + dm) : R(0);
+  return s > R(0) ? dvd(R(2) * s, dp + dm) : R(0);
 }
 
 // Fast magnetosonic speed from a^2 = gamma p / rho, |B|^2 / rho and B_n^2 / rho.
 template <typename R>
 __device__ __forceinline__ R fast_speed(R gamma, R rho, R p, R bn, R b1, R b2) {
-  R irho = R(1) / rho;
+  R irho = rcp(rho);
   R a2 = (gamma * p) * irho;
   R bb = (bn * bn + b1 * b1) + b2 * b2;
   R ca2 = bb * irho;
@@ -93,6 +100,15 @@ __device__ __forceinline__ void physical(const Prim<R>& w, R bn, R igm1, Cons<R>
   c.pt = pt;
 }
 
+// Total energy and total pressure of a face state (same expressions as above).
+template <typename R>
+__device__ __forceinline__ void thermo(const Prim<R>& w, R bn, R igm1, R& e, R& pt) {
+  R v2sq = (w.un * w.un + w.v1 * w.v1) + w.v2 * w.v2;
+  R bb = (bn * bn + w.b1 * w.b1) + w.b2 * w.b2;
+  pt = w.p + R(0.5) * bb;
+  e = (w.p * igm1 + R(0.5) * (w.rho * v2sq)) + R(0.5) * bb;
+}
+
 // Outer signal speeds S_L = min(v_n) - max(c_f), S_R = max(v_n) + max(c_f) and the
 // face's largest |speed| for the CFL condition.
 template <typename R>
@@ -125,7 +141,7 @@ __device__ __forceinline__ void flux_hll(R gamma, R igm1, const Prim<R>& l, cons
 #pragma unroll
     for (int q = 0; q < 7; ++q) f[q] = cr.f[q];
   } else {
-    R ih = R(1) / (sr - sl);
+    R ih = rcp(sr - sl);
     R slr = sr * sl;
 #pragma unroll
     for (int q = 0; q < 7; ++q) f[q] = ((sr * cl.f[q] - sl * cr.f[q]) + slr * (cr.u[q] - cl.u[q])) * ih;
@@ -140,12 +156,12 @@ struct Star {
 };
 
 template <typename R>
-__device__ __forceinline__ void hlld_star(const Prim<R>& w, const Cons<R>& c, R bn, R sa, R sm,
-                                          R pts, Star<R>& st) {
+__device__ __forceinline__ void hlld_star(const Prim<R>& w, R ea, R pta, R bn, R sa, R sm, R pts,
+                                          Star<R>& st) {
   R sua = sa - w.un;
   R da = sua * w.rho;
   R sam = sa - sm;
-  R isam = R(1) / sam;
+  R isam = rcp(sam);
   R rhos = da * isam;
   R t = da * sam;
   R bn2 = bn * bn;
@@ -157,7 +173,7 @@ __device__ __forceinline__ void hlld_star(const Prim<R>& w, const Cons<R>& c, R 
     b1s = w.b1;
     b2s = w.b2;
   } else {
-    R iden = R(1) / den;
+    R iden = rcp(den);
     R tv = (bn * (sm - w.un)) * iden;
     R tb = (da * sua - bn2) * iden;
     v1s = w.v1 - w.b1 * tv;
@@ -167,7 +183,7 @@ __device__ __forceinline__ void hlld_star(const Prim<R>& w, const Cons<R>& c, R 
   }
   R vba = (w.un * bn + w.v1 * w.b1) + w.v2 * w.b2;
   R vbs = (sm * bn + v1s * b1s) + v2s * b2s;
-  st.e = (((sua * c.u[4] - c.pt * w.un) + pts * sm) + bn * (vba - vbs)) * isam;
+  st.e = (((sua * ea - pta * w.un) + pts * sm) + bn * (vba - vbs)) * isam;
   st.rho = rhos;
   st.v1 = v1s;
   st.v2 = v2s;
@@ -176,72 +192,79 @@ __device__ __forceinline__ void hlld_star(const Prim<R>& w, const Cons<R>& c, R 
   st.vb = vbs;
 }
 
-// HLLD flux: fans S_L < S*_L < S_M < S*_R < S_R.
+template <typename R>
+__device__ __forceinline__ Prim<R> pick(bool c, const Prim<R>& a, const Prim<R>& b) {
+  Prim<R> w;
+  w.rho = c ? a.rho : b.rho; w.un = c ? a.un : b.un; w.v1 = c ? a.v1 : b.v1;
+  w.v2 = c ? a.v2 : b.v2; w.b1 = c ? a.b1 : b.b1; w.b2 = c ? a.b2 : b.b2; w.p = c ? a.p : b.p;
+  return w;
+}
+
+template <typename R>
+__device__ __forceinline__ Star<R> pick(bool c, const Star<R>& a, const Star<R>& b) {
+  Star<R> s;
+  s.rho = c ? a.rho : b.rho; s.v1 = c ? a.v1 : b.v1; s.v2 = c ? a.v2 : b.v2;
+  s.b1 = c ? a.b1 : b.b1; s.b2 = c ? a.b2 : b.b2; s.e = c ? a.e : b.e; s.vb = c ? a.vb : b.vb;
+  return s;
+}
+
+// HLLD flux: fans S_L < S*_L < S_M < S*_R < S_R.  The region is found from the
+// speeds and star densities first; then only the side whose states the flux
+// is built from (left for S*_L >= 0 or S_M >= 0 > S*_L, right otherwise) gets
+// its conserved vector and physical flux evaluated, with the same expressions
+// F*_a = F_a + S_a (U*_a - U_a) and F**_a = F*_a + S*_a (U**_a - U*_a).
 template <typename R>
 __device__ __forceinline__ void flux_hlld(R gamma, R igm1, const Prim<R>& l, const Prim<R>& r, R bn,
                                           R* f, R& cmax) {
-  Cons<R> cl, cr;
-  physical(l, bn, igm1, cl);
-  physical(r, bn, igm1, cr);
   R sl, sr;
   outer_speeds(gamma, l, r, bn, sl, sr, cmax);
-  if (sl >= R(0)) {
+  if (sl >= R(0) || sr <= R(0)) {  // supersonic: upwind physical flux
+    Cons<R> c;
+    physical(sl >= R(0) ? l : r, bn, igm1, c);
 #pragma unroll
-    for (int q = 0; q < 7; ++q) f[q] = cl.f[q];
+    for (int q = 0; q < 7; ++q) f[q] = c.f[q];
     return;
   }
-  if (sr <= R(0)) {
-#pragma unroll
-    for (int q = 0; q < 7; ++q) f[q] = cr.f[q];
-    return;
-  }
+  R el, ptl, er, ptr;
+  thermo(l, bn, igm1, el, ptl);
+  thermo(r, bn, igm1, er, ptr);
   R dl = (sl - l.un) * l.rho;
   R dr = (sr - r.un) * r.rho;
-  R iden = R(1) / (dr - dl);
-  R sm = (((dr * r.un - dl * l.un) - cr.pt) + cl.pt) * iden;
-  R pts = ((dr * cl.pt - dl * cr.pt) + (dr * dl) * (r.un - l.un)) * iden;
+  R iden = rcp(dr - dl);
+  R sm = (((dr * r.un - dl * l.un) - ptr) + ptl) * iden;
+  R pts = ((dr * ptl - dl * ptr) + (dr * dl) * (r.un - l.un)) * iden;
   Star<R> stl, str;
-  hlld_star(l, cl, bn, sl, sm, pts, stl);
-  hlld_star(r, cr, bn, sr, sm, pts, str);
-  R usl[7] = {stl.rho, stl.rho * sm, stl.rho * stl.v1, stl.rho * stl.v2, stl.e, stl.b1, stl.b2};
-  R usr[7] = {str.rho, str.rho * sm, str.rho * str.v1, str.rho * str.v2, str.e, str.b1, str.b2};
+  hlld_star(l, el, ptl, bn, sl, sm, pts, stl);
+  hlld_star(r, er, ptr, bn, sr, sm, pts, str);
   R sql = dsqrt(stl.rho), sqr = dsqrt(str.rho);
   R abn = dabs(bn);
-  R ssl = sm - abn / sql;
-  R ssr = sm + abn / sqr;
-  if (ssl >= R(0)) {
+  R ssl = sm - dvd(abn, sql);
+  R ssr = sm + dvd(abn, sqr);
+  const bool star_l = ssl >= R(0);
+  const bool star_r = !star_l && !(sm >= R(0)) && !(ssr >= R(0));
+  const bool dstar = !star_l && !star_r;
+  const bool left = star_l || (dstar && sm >= R(0));
+  const Prim<R> w = pick(left, l, r);
+  const Star<R> st = pick(left, stl, str);
+  const R sa = left ? sl : sr;
+  Cons<R> c;
+  physical(w, bn, igm1, c);
+  R us[7] = {st.rho, st.rho * sm, st.rho * st.v1, st.rho * st.v2, st.e, st.b1, st.b2};
 #pragma unroll
-    for (int q = 0; q < 7; ++q) f[q] = cl.f[q] + sl * (usl[q] - cl.u[q]);
-    return;
-  }
-  if (!(sm >= R(0)) && !(ssr >= R(0))) {
+  for (int q = 0; q < 7; ++q) f[q] = c.f[q] + sa * (us[q] - c.u[q]);
+  if (dstar) {
+    R sgn = bn > R(0) ? R(1) : (bn < R(0) ? R(-1) : R(0));
+    R isq = rcp(sql + sqr);
+    R v1ss = ((sql * stl.v1 + sqr * str.v1) + (str.b1 - stl.b1) * sgn) * isq;
+    R v2ss = ((sql * stl.v2 + sqr * str.v2) + (str.b2 - stl.b2) * sgn) * isq;
+    R b1ss = ((sql * str.b1 + sqr * stl.b1) + (sql * sqr) * ((str.v1 - stl.v1) * sgn)) * isq;
+    R b2ss = ((sql * str.b2 + sqr * stl.b2) + (sql * sqr) * ((str.v2 - stl.v2) * sgn)) * isq;
+    R vbss = (sm * bn + v1ss * b1ss) + v2ss * b2ss;
+    R ess = left ? stl.e - (sql * (stl.vb - vbss)) * sgn : str.e + (sqr * (str.vb - vbss)) * sgn;
+    R ssa = left ? ssl : ssr;
+    R uss[7] = {st.rho, st.rho * sm, st.rho * v1ss, st.rho * v2ss, ess, b1ss, b2ss};
 #pragma unroll
-    for (int q = 0; q < 7; ++q) f[q] = cr.f[q] + sr * (usr[q] - cr.u[q]);
-    return;
-  }
-  R sgn = bn > R(0) ? R(1) : (bn < R(0) ? R(-1) : R(0));
-  R isq = R(1) / (sql + sqr);
-  R v1ss = ((sql * stl.v1 + sqr * str.v1) + (str.b1 - stl.b1) * sgn) * isq;
-  R v2ss = ((sql * stl.v2 + sqr * str.v2) + (str.b2 - stl.b2) * sgn) * isq;
-  R b1ss = ((sql * str.b1 + sqr * stl.b1) + (sql * sqr) * ((str.v1 - stl.v1) * sgn)) * isq;
-  R b2ss = ((sql * str.b2 + sqr * stl.b2) + (sql * sqr) * ((str.v2 - stl.v2) * sgn)) * isq;
-  R vbss = (sm * bn + v1ss * b1ss) + v2ss * b2ss;
-  if (sm >= R(0)) {
-    R ess = stl.e - (sql * (stl.vb - vbss)) * sgn;
-    R uss[7] = {stl.rho, stl.rho * sm, stl.rho * v1ss, stl.rho * v2ss, ess, b1ss, b2ss};
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      R fs = cl.f[q] + sl * (usl[q] - cl.u[q]);
-      f[q] = fs + ssl * (uss[q] - usl[q]);
-    }
-  } else {
-    R ess = str.e + (sqr * (str.vb - vbss)) * sgn;
-    R uss[7] = {str.rho, str.rho * sm, str.rho * v1ss, str.rho * v2ss, ess, b1ss, b2ss};
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      R fs = cr.f[q] + sr * (usr[q] - cr.u[q]);
-      f[q] = fs + ssr * (uss[q] - usr[q]);
-    }
+    for (int q = 0; q < 7; ++q) f[q] = f[q] + ssa * (uss[q] - us[q]);
   }
 }
 

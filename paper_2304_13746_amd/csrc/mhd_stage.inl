@@ -68,7 +68,7 @@ __device__ __forceinline__ void to_prim(R rho, R mx, R my, R mz, R en, R bxl, R 
   c.bx = R(0.5) * (bxl + bxr);
   c.by = R(0.5) * (byl + byr);
   c.bz = R(0.5) * (bzl + bzr);
-  R irho = R(1) / rho;
+  R irho = rcp(rho);
   c.vx = mx * irho;
   c.vy = my * irho;
   c.vz = mz * irho;
@@ -216,12 +216,45 @@ struct Smem {
   R ez[T::NE], ex[T::NE], ey[T::NE];
 };
 
+// Per-thread march values kept in LDS instead of registers: for FP64 with the
+// 16x16 tile, where the register file, not LDS, already limits the kernel to
+// one block per CU.
+template <typename R, int TX, int TY>
+struct Carry {
+  static constexpr bool in_lds = sizeof(R) == 8 && TX == 16;
+  static constexpr int NT = Tile<TX, TY>::NT;
+  static constexpr int N = in_lds ? NT : 1;
+  R part[5][N], fzp[5][N], um[5][N];
+};
+
+template <typename R, int TX, int TY>
+struct SmemAll {
+  Smem<R, TX, TY> s;
+  Carry<R, TX, TY> c;
+};
+
+// Waves per SIMD the register allocation must allow: FP32 three (<= 168
+// VGPRs, three 4-wave blocks per CU), FP64 two (<= 256 VGPRs).
+#ifndef MHD_WAVES_F32
+#define MHD_WAVES_F32 3
+#endif
+#ifndef MHD_WAVES_F64
+#define MHD_WAVES_F64 2
+#endif
+template <typename R>
+struct Occupancy {
+  static constexpr int waves = sizeof(R) == 4 ? MHD_WAVES_F32 : MHD_WAVES_F64;
+};
+
 template <typename R, int SOLVER, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY + 2 * (TX + TY))
+__attribute__((amdgpu_waves_per_eu(Occupancy<R>::waves)))
 stage_kernel(StageArgs<R> a) {
   using T = Tile<TX, TY>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Smem<R, TX, TY>& S = *reinterpret_cast<Smem<R, TX, TY>*>(smem_raw);
+  SmemAll<R, TX, TY>& SA = *reinterpret_cast<SmemAll<R, TX, TY>*>(smem_raw);
+  Smem<R, TX, TY>& S = SA.s;
+  constexpr bool CL = Carry<R, TX, TY>::in_lds;
 
   // XCD-aware order: the hardware deals blocks round-robin over 8 XCDs; give
   // each XCD a contiguous run of spatially adjacent tiles so halos hit its L2.
@@ -274,9 +307,14 @@ stage_kernel(StageArgs<R> a) {
   R top7[7];           // z-face left state from the top of cell m-1
   R bx_m = 0, by_m = 0, bz_m = 0;     // face B of plane m (own column)
   R bx_p = 0, by_p = 0;                // face B of plane m-1
-  R u_m[5] = {0, 0, 0, 0, 0};          // conserved of plane m (own column)
-  R part[5] = {0, 0, 0, 0, 0};         // U - tau_x dFx - tau_y dFy of cell m-1
-  R fz_prev[5] = {0, 0, 0, 0, 0};      // z-flux at (m-1)-1/2
+  // conserved of plane m (own column), U - tau_x dFx - tau_y dFy of cell m-1 and
+  // the z-flux at (m-1)-1/2: registers, or this thread's LDS slots
+  R u_m[5] = {0, 0, 0, 0, 0};
+  R part[5] = {0, 0, 0, 0, 0};
+  R fz_prev[5] = {0, 0, 0, 0, 0};
+  auto um = [&](int q) -> R& { if constexpr (CL) return SA.c.um[q][t]; else return u_m[q]; };
+  auto pt_ = [&](int q) -> R& { if constexpr (CL) return SA.c.part[q][t]; else return part[q]; };
+  auto fzp = [&](int q) -> R& { if constexpr (CL) return SA.c.fzp[q][t]; else return fz_prev[q]; };
   R zc_prev = 0;                       // its signal speed
   R cxy_prev = 0;                      // x,y part of inv_dt of cell m-1
   R xey_prev = 0, xmass_prev = 0;      // own x-face E_y part and mass flux, plane m-1
@@ -297,7 +335,7 @@ stage_kernel(StageArgs<R> a) {
     load_raw(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
     to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w0);
     bx_m = r.bxl; by_m = r.byl; bz_m = r.bzl;
-    u_m[0] = r.rho; u_m[1] = r.mx; u_m[2] = r.my; u_m[3] = r.mz; u_m[4] = r.en;
+    um(0) = r.rho; um(1) = r.mx; um(2) = r.my; um(3) = r.mz; um(4) = r.en;
     const int iw = T::w(ci, cj);
     S.w[0][iw] = w0.rho; S.w[1][iw] = w0.vx; S.w[2][iw] = w0.vy; S.w[3][iw] = w0.vz;
     S.w[4][iw] = w0.bx; S.w[5][iw] = w0.by; S.w[6][iw] = w0.bz; S.w[7][iw] = w0.p;
@@ -494,7 +532,7 @@ stage_kernel(StageArgs<R> a) {
       const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
 #pragma unroll
       for (int q = 0; q < 5; ++q)
-        part_new[q] = (u_m[q] - tau_x * (S.xcons[q][e_e] - S.xcons[q][ex_me])) -
+        part_new[q] = (um(q) - tau_x * (S.xcons[q][e_e] - S.xcons[q][ex_me])) -
                       tau_y * (S.ycons[q][e_n] - S.ycons[q][ex_me]);
       if constexpr (MODE != MODE_STAGE2) {
         R cx = S.xcmax[ex_me] > S.xcmax[e_e] ? S.xcmax[ex_me] : S.xcmax[e_e];
@@ -514,7 +552,7 @@ stage_kernel(StageArgs<R> a) {
       if constexpr (MODE != MODE_MEASURE) {
         R un[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) un[q] = part[q] - tau_z * (fz.cons[q] - fz_prev[q]);
+        for (int q = 0; q < 5; ++q) un[q] = pt_(q) - tau_z * (fz.cons[q] - fzp(q));
         const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
         R bxn = (bx_p - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
         R byn = (by_p - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
@@ -550,9 +588,9 @@ stage_kernel(StageArgs<R> a) {
     // ---------------- shift the march registers
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      part[q] = part_new[q];
-      fz_prev[q] = fz.cons[q];
-      u_m[q] = u_n[q];
+      pt_(q) = part_new[q];
+      fzp(q) = fz.cons[q];
+      um(q) = u_n[q];
     }
     zc_prev = fz.cmax;
     cxy_prev = cxy_new;
@@ -593,7 +631,7 @@ stage_kernel(StageArgs<R> a) {
 template <typename R, int SOLVER, int MODE, int TX, int TY>
 static hipError_t launch_one(const StageArgs<R>& a, hipStream_t st, bool prepare) {
   using T = Tile<TX, TY>;
-  const size_t lds = sizeof(Smem<R, TX, TY>);
+  const size_t lds = sizeof(SmemAll<R, TX, TY>);
   auto fn = stage_kernel<R, SOLVER, MODE, TX, TY>;
   if (prepare)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),

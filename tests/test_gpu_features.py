@@ -1,0 +1,158 @@
+"""GPU tests of the full-size workload, diagnostics, checkpoint/resume, error
+latching, launch-shape invariance and determinism (all through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import FIELDS, bit_equal, gpu_box, max_rel, need_gpu, run_both
+from paper_2304_13746_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def turb256():
+    s = I.turbulence(256, seed=2304, kpeak=4.0, mach=0.5, rho0=1.0, p0=0.6, b0=(0.2, 0.0, 0.0))
+    s.pop("_l")
+    return s
+
+
+def test_full_size_256_fp64_bit_exact(turb256):
+    """The benchmark workload (256^3 turbulence, default launch shape) for one
+    RK2 cycle: bit-identical to the oracle, including the next dt."""
+    need_gpu()
+    g, o, gd, od, (tg, to) = run_both(turb256, (256, 256, 256), 1)
+    print("256^3 fp64 max rel", max_rel(g, o))
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+
+
+def test_full_size_256_fp32(turb256):
+    need_gpu()
+    s = I.to_float32_exact(turb256)
+    g, o, gd, od, _ = run_both(s, (256, 256, 256), 1, precision="fp32")
+    err = max_rel(g, o)
+    print("256^3 fp32 max rel", err)
+    assert err <= 1e-5
+    assert abs(gd[-1] - od[-1]) <= 1e-5 * od[-1]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_diagnostics_match_oracle(precision):
+    """Compensated FP64 totals and div B of the GPU state agree with the
+    oracle's on the same state to 1e-12 relative; div B stays at round-off."""
+    need_gpu()
+    s = I.orszag_tang(32)
+    if precision == "fp32":
+        s = I.to_float32_exact(s)
+    box = gpu_box((32, 32, 32), precision=precision)
+    box.set_state(s)
+    box.step(5)
+    g, _, _, _ = box.get_state_numpy()
+    d = box.diagnostics()
+    ref = O.diagnostics(O.Params(32, 32, 32), g)
+    assert d["status"] == 0
+    for k in ("mass", "energy"):
+        assert abs(d[k] - ref[k]) <= 1e-12 * abs(ref[k])
+    vol = 1.0 / 32 ** 3
+    for c, f in enumerate(("mx", "my", "mz")):
+        assert abs(d["mom"][c] - ref["mom"][c]) <= 1e-12 * np.sum(np.abs(g[f])) * vol
+    for c, f in enumerate(("bx", "by", "bz")):
+        assert abs(d["bflux"][c] - ref["bflux"][c]) <= 1e-12 * max(np.sum(np.abs(g[f])) * vol, 1e-30)
+    assert d["divb_max"] == pytest.approx(ref["divb_max"], rel=1e-12, abs=1e-300)
+    assert d["divb_rms"] == pytest.approx(ref["divb_rms"], rel=1e-10, abs=1e-300)
+    bmax = max(np.max(np.abs(g[f])) for f in ("bx", "by", "bz"))
+    tol = 1e-14 if precision == "fp64" else 1e-6
+    assert d["divb_max"] / 32 / bmax <= tol
+
+
+def test_checkpoint_resume_bit_exact():
+    """step(3); get (state, t, dt_next); set into a fresh context; step(4)
+    equals step(7) bit for bit."""
+    need_gpu()
+    s = I.orszag_tang(32)
+    a = gpu_box((32, 32, 32))
+    a.set_state(s)
+    a.step(7)
+    ga, ta, da, _ = a.get_state_numpy()
+    b = gpu_box((32, 32, 32))
+    b.set_state(s)
+    b.step(3)
+    mid, tm, dm, _ = b.get_state()
+    c = gpu_box((32, 32, 32))
+    c.set_state(mid, tm, dm)
+    c.step(4)
+    gc, tc, dc, _ = c.get_state_numpy()
+    assert bit_equal(ga, gc) and ta == tc and da == dc
+
+
+def test_nonphysical_state_is_latched_and_reported():
+    """A cell with negative pressure is detected on the device; the next
+    synchronising call returns MHD_ERR_NONPHYSICAL; another context is
+    unaffected; set_state clears the latch."""
+    need_gpu()
+    from paper_2304_13746_amd import _lib
+    s = I.orszag_tang(16)
+    bad = {k: v.copy() for k, v in s.items()}
+    bad["en"][3, 5, 7] = 1e-6  # internal energy < 0 there
+    good_box = gpu_box((16, 16, 16))
+    good_box.set_state(s)
+    box = gpu_box((16, 16, 16))
+    box.set_state(bad, 0.0, 1e-3)
+    box.step(1)
+    good_box.step(1)
+    _, _, _, rc = box.get_state(check=False)
+    assert rc == _lib.MHD_ERR_NONPHYSICAL
+    assert box.diagnostics()["status"] == 1
+    _, _, _, rc = good_box.get_state(check=False)
+    assert rc == _lib.MHD_OK
+    box.set_state(s)
+    box.step(1)
+    _, _, _, rc = box.get_state(check=False)
+    assert rc == _lib.MHD_OK
+
+
+@pytest.mark.parametrize("tile,zchunk", [(1, 16), (1, 7), (2, 32), (2, 3)])
+def test_launch_shape_invariance_fp64(tile, zchunk):
+    """Tile shape and z-chunk length change only how work is split: FP64
+    results are bit-identical to the oracle for every launch shape."""
+    need_gpu()
+    dims = (40, 36, 28)
+    s = I.turbulence(dims, seed=11, kpeak=2.0, mach=0.9, b0=(0.1, 0.3, -0.2))
+    s.pop("_l")
+    h = 1.0 / 40
+    g, o, gd, od, _ = run_both(s, dims, 3, l=(40 * h, 36 * h, 28 * h), tile=tile, zchunk=zchunk)
+    assert bit_equal(g, o)
+    assert gd == od
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_repeat_runs_identical(precision):
+    """Two runs of the same input give identical bits (no races)."""
+    need_gpu()
+    s = I.orszag_tang_3d(48)
+    outs = []
+    for _ in range(2):
+        box = gpu_box((48, 48, 48), precision=precision)
+        box.set_state(s)
+        box.step(5)
+        outs.append(box.get_state_numpy()[0])
+    assert bit_equal(outs[0], outs[1])
+
+
+def test_t_stop_clips_last_step():
+    """With t_stop the cycle that would pass it is shortened to land on it;
+    later cycles take zero steps and leave the state unchanged."""
+    need_gpu()
+    s = I.orszag_tang(16)
+    box = gpu_box((16, 16, 16))
+    box.set_state(s)
+    box.step(3)
+    _, t3, dt3, _ = box.get_state()
+    t_stop = t3 + 0.5 * dt3
+    box.step(1, t_stop=t_stop)
+    g1, t4, _, _ = box.get_state_numpy()
+    assert t4 == t_stop or abs(t4 - t_stop) <= 1e-15 * t_stop
+    box.step(2, t_stop=t_stop)
+    g2, t5, _, _ = box.get_state_numpy()
+    assert t5 == t4 and bit_equal(g1, g2)
