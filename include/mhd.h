@@ -116,9 +116,16 @@ int mhd_get_state(mhd_ctx* ctx, const mhd_state_view* dst, double* t, double* dt
  * state.  Synchronises the stream. */
 int mhd_get_diagnostics(mhd_ctx* ctx, mhd_diag* out);
 
-/* Advance n contexts by nsteps[i] cycles each with persistent launches on one
- * stream (every context must share precision, solver and integrator).  Each box
- * keeps its own step size.  Asynchronous. */
+/* Advance n (0 <= n <= 4096) contexts by nsteps[i] >= 0 cycles each on one
+ * stream (NULL: the stream of ctxs[0]).  Each stage of a cycle is one launch
+ * whose blocks cover the tiles of every box still stepping (up to 64 boxes per
+ * launch), followed by one cycle-control launch for all of them; each box keeps
+ * its own step size, time and status latch, and gives the same bits as
+ * mhd_step on it alone.  All contexts must share device, precision, solver,
+ * integrator and tile shape (else MHD_ERR_UNSUPPORTED); a null entry or a
+ * negative count is MHD_ERR_INVALID_ARG.  The contexts' own streams are not
+ * synchronised with: order them against the batch stream first.  Asynchronous,
+ * allocation-free, capture-safe. */
 int mhd_step_batch(mhd_ctx* const* ctxs, const int* nsteps, int n, void* stream);
 
 /* Release the context (not the borrowed workspace).  Safe on NULL. */

@@ -21,9 +21,11 @@ struct mhd_ctx {
   void* buf[2][8];   // two state buffers of 8 fields
   int cur;           // buffer holding the state
   Scalars* sc;       // device scalars
+  BoxDesc* desc;     // device copy of this box's descriptor
   double* diag_part; // per-block diagnostic partials
   int tile, lz;
   int diag_blocks;
+  int tiles;         // stage-kernel blocks for this box
 };
 
 namespace {
@@ -76,19 +78,33 @@ __global__ void k_init_dt(Scalars* s) {
   st_agent(&s->invdt_bits, 0ull);
 }
 
-__global__ void k_begin(Scalars* s, double t_stop) {
-  st_agent(&s->dt, clip_step(ld_agent(&s->dt_next), ld_agent(&s->t), t_stop));
+// cycle control for up to kMaxBatch boxes, one thread per box
+struct CtlArgs {
+  int n;
+  int pad;
+  Scalars* sc[kMaxBatch];
+  double t_stop[kMaxBatch];
+};
+
+__global__ void k_begin(CtlArgs a) {
+  const int i = threadIdx.x;
+  if (i >= a.n) return;
+  Scalars* s = a.sc[i];
+  st_agent(&s->dt, clip_step(ld_agent(&s->dt_next), ld_agent(&s->t), a.t_stop[i]));
   st_agent(&s->invdt_bits, 0ull);
 }
 
 // end of a cycle: advance t, take the step measured during its first stage,
 // clip the next cycle's step
-__global__ void k_end(Scalars* s, double t_stop) {
+__global__ void k_end(CtlArgs a) {
+  const int i = threadIdx.x;
+  if (i >= a.n) return;
+  Scalars* s = a.sc[i];
   const double t = ld_agent(&s->t) + ld_agent(&s->dt);
   const double dtn = ld_agent(&s->cfl) / invdt_max(s);
   st_agent(&s->t, t);
   st_agent(&s->dt_next, dtn);
-  st_agent(&s->dt, clip_step(dtn, t, t_stop));
+  st_agent(&s->dt, clip_step(dtn, t, a.t_stop[i]));
   st_agent(&s->invdt_bits, 0ull);
 }
 
@@ -190,23 +206,82 @@ void fields_of(const mhd_state_view* v, void* out[8]) {
   out[4] = v->en; out[5] = v->bx; out[6] = v->by; out[7] = v->bz;
 }
 
-hipError_t launch_stage(mhd_ctx* c, int mode, int src, int dst) {
-  StageLaunch l;
-  for (int f = 0; f < 8; ++f) {
-    l.src[f] = c->buf[src][f];
-    l.dst[f] = c->buf[dst][f];
+// One stage launch over n contexts sharing precision, solver and tile; src[i]
+// is the buffer box i reads.  Batches beyond kMaxBatch go out in chunks.
+hipError_t launch_stage(mhd_ctx* const* c, const int* src, int n, int mode, hipStream_t st) {
+  for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+    const int m = n - i0 < kMaxBatch ? n - i0 : kMaxBatch;
+    BatchArgs ba = {};
+    ba.nbox = m;
+    ba.mode = mode;
+    int g = 0;
+    for (int i = 0; i < m; ++i) {
+      ba.desc[i] = c[i0 + i]->desc;
+      ba.start[i] = g;
+      ba.src[i] = (unsigned char)src[i0 + i];
+      g += c[i0 + i]->tiles;
+    }
+    ba.start[m] = g;
+    ba.total = g;
+    const mhd_ctx* c0 = c[i0];
+    hipError_t e = c0->p.precision == MHD_FP32 ? stage_f32(ba, c0->tile, c0->p.riemann, st, false)
+                                               : stage_f64(ba, c0->tile, c0->p.riemann, st, false);
+    if (e != hipSuccess) return e;
   }
-  l.nx = c->p.nx;
-  l.ny = c->p.ny;
-  l.nz = c->p.nz;
-  l.lz = c->lz;
-  for (int d = 0; d < 3; ++d) l.idl[d] = c->idl[d];
-  l.gamma = c->p.gamma;
-  l.sc = c->sc;
-  l.tile = c->tile;
-  l.solver = c->p.riemann;
-  l.mode = mode;
-  return c->p.precision == MHD_FP32 ? stage_f32(l, c->stream, false) : stage_f64(l, c->stream, false);
+  return hipSuccess;
+}
+
+hipError_t launch_ctl(bool begin, mhd_ctx* const* c, int n, const double* t_stop, hipStream_t st) {
+  for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+    const int m = n - i0 < kMaxBatch ? n - i0 : kMaxBatch;
+    CtlArgs a = {};
+    a.n = m;
+    for (int i = 0; i < m; ++i) {
+      a.sc[i] = c[i0 + i]->sc;
+      a.t_stop[i] = t_stop ? t_stop[i0 + i] : 0.0;
+    }
+    if (begin)
+      hipLaunchKernelGGL(k_begin, dim3(1), dim3(kMaxBatch), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_end, dim3(1), dim3(kMaxBatch), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Advance n contexts (same precision, solver, tile, integrator) by nsteps[i]
+// cycles each on one stream; every box keeps its own dt and t_stop.
+int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop, hipStream_t st) {
+  int maxs = 0;
+  for (int i = 0; i < n; ++i) maxs = nsteps[i] > maxs ? nsteps[i] : maxs;
+  if (maxs == 0) return MHD_OK;
+  mhd_ctx* act[4096];
+  int src[4096];
+  double ts[4096];
+  if (n > 4096) return MHD_ERR_INVALID_ARG;
+  int m = 0;
+  for (int i = 0; i < n; ++i)
+    if (nsteps[i] > 0) { act[m] = c[i]; ts[m] = t_stop ? t_stop[i] : 0.0; ++m; }
+  if (launch_ctl(true, act, m, ts, st) != hipSuccess) return MHD_ERR_HIP;
+  const bool rk2 = c[0]->p.integrator == MHD_RK2;
+  for (int cyc = 0; cyc < maxs; ++cyc) {
+    m = 0;
+    for (int i = 0; i < n; ++i)
+      if (nsteps[i] > cyc) { act[m] = c[i]; ts[m] = t_stop ? t_stop[i] : 0.0; ++m; }
+    for (int i = 0; i < m; ++i) src[i] = act[i]->cur;
+    // U_1 = S_dt(U_0), measuring the next dt
+    if (launch_stage(act, src, m, 0, st) != hipSuccess) return MHD_ERR_HIP;
+    if (rk2) {
+      // U^{n+1} = 1/2 S_dt(U_1) + 1/2 U_0, written over U_0
+      for (int i = 0; i < m; ++i) src[i] = 1 - act[i]->cur;
+      if (launch_stage(act, src, m, 1, st) != hipSuccess) return MHD_ERR_HIP;
+    } else {
+      for (int i = 0; i < m; ++i) act[i]->cur = 1 - act[i]->cur;
+    }
+    if (launch_ctl(false, act, m, ts, st) != hipSuccess) return MHD_ERR_HIP;
+  }
+  return MHD_OK;
 }
 
 int choose_lz(int tile, int nx, int ny, int nz) {
@@ -241,8 +316,8 @@ extern "C" {
 size_t mhd_workspace_bytes(const mhd_params* p) {
   if (!grid_ok(p)) return 0;
   if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return 0;
-  return align_up(sizeof(Scalars)) + align_up(sizeof(double) * kDiagBlocks * kDiagVals) +
-         16 * field_bytes(p);
+  return align_up(sizeof(Scalars)) + align_up(sizeof(BoxDesc)) +
+         align_up(sizeof(double) * kDiagBlocks * kDiagVals) + 16 * field_bytes(p);
 }
 
 int mhd_create(const mhd_params* p, mhd_ctx** out) {
@@ -281,6 +356,8 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   char* w = (char*)p->workspace;
   c->sc = (Scalars*)w;
   w += align_up(sizeof(Scalars));
+  c->desc = (BoxDesc*)w;
+  w += align_up(sizeof(BoxDesc));
   c->diag_part = (double*)w;
   w += align_up(sizeof(double) * kDiagBlocks * kDiagVals);
   const size_t fb = field_bytes(p);
@@ -294,11 +371,29 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   c->lz = p->zchunk > 0 ? (p->zchunk < p->nz ? p->zchunk : p->nz) : choose_lz(tile, p->nx, p->ny, p->nz);
   c->diag_blocks = kDiagBlocks;
   // raise the dynamic-LDS limit of this tile's kernels (host-side attribute)
-  StageLaunch l = {};
-  l.tile = tile;
-  l.solver = p->riemann;
-  hipError_t e = p->precision == MHD_FP32 ? stage_f32(l, nullptr, true) : stage_f64(l, nullptr, true);
+  BatchArgs none = {};
+  hipError_t e = p->precision == MHD_FP32 ? stage_f32(none, tile, p->riemann, nullptr, true)
+                                          : stage_f64(none, tile, p->riemann, nullptr, true);
   if (e != hipSuccess) {
+    free(c);
+    return MHD_ERR_HIP;
+  }
+  BoxDesc d = {};
+  for (int b = 0; b < 2; ++b)
+    for (int f = 0; f < 8; ++f) d.buf[b][f] = c->buf[b][f];
+  d.nx = p->nx;
+  d.ny = p->ny;
+  d.nz = p->nz;
+  d.ntx = (p->nx + tx - 1) / tx;
+  d.nty = (p->ny + ty - 1) / ty;
+  d.lz = c->lz;
+  d.nzc = (p->nz + c->lz - 1) / c->lz;
+  for (int k = 0; k < 3; ++k) d.idl[k] = c->idl[k];
+  d.gamma = p->gamma;
+  d.sc = c->sc;
+  c->tiles = d.ntx * d.nty * d.nzc;
+  if (hipMemcpyAsync(c->desc, &d, sizeof(d), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
     free(c);
     return MHD_ERR_HIP;
   }
@@ -327,8 +422,8 @@ int mhd_set_state(mhd_ctx* c, const mhd_state_view* v, double t, double dt_next)
   if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
   if (!(dt_next > 0.0)) {
     // eq. (cfl) on the initial state: the stage kernel in measuring mode
-    hipError_t e = launch_stage(c, 2, 0, 1);
-    if (e != hipSuccess) return MHD_ERR_HIP;
+    const int src0 = 0;
+    if (launch_stage(&c, &src0, 1, 2, c->stream) != hipSuccess) return MHD_ERR_HIP;
     hipLaunchKernelGGL(k_init_dt, dim3(1), dim3(1), 0, c->stream, c->sc);
     if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
   }
@@ -337,23 +432,7 @@ int mhd_set_state(mhd_ctx* c, const mhd_state_view* v, double t, double dt_next)
 
 int mhd_step(mhd_ctx* c, int nsteps, double t_stop) {
   if (!c || nsteps < 0) return MHD_ERR_INVALID_ARG;
-  if (nsteps == 0) return MHD_OK;
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, c->stream, c->sc, t_stop);
-  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
-  for (int n = 0; n < nsteps; ++n) {
-    const int a = c->cur, b = 1 - c->cur;
-    hipError_t e = launch_stage(c, 0, a, b);  // U_1 = S_dt(U_0), measures dt
-    if (e != hipSuccess) return MHD_ERR_HIP;
-    if (c->p.integrator == MHD_RK2) {
-      e = launch_stage(c, 1, b, a);  // U^{n+1} = 1/2 S_dt(U_1) + 1/2 U_0
-      if (e != hipSuccess) return MHD_ERR_HIP;
-    } else {
-      c->cur = b;
-    }
-    hipLaunchKernelGGL(k_end, dim3(1), dim3(1), 0, c->stream, c->sc, t_stop);
-    if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
-  }
-  return MHD_OK;
+  return step_group(&c, &nsteps, 1, &t_stop, c->stream);
 }
 
 int mhd_get_state(mhd_ctx* c, const mhd_state_view* v, double* t, double* dt_next) {
@@ -412,17 +491,19 @@ int mhd_get_diagnostics(mhd_ctx* c, mhd_diag* out) {
 }
 
 int mhd_step_batch(mhd_ctx* const* ctxs, const int* nsteps, int n, void* stream) {
-  if (!ctxs || !nsteps || n < 0) return MHD_ERR_INVALID_ARG;
+  if (!ctxs || !nsteps || n < 0 || n > 4096) return MHD_ERR_INVALID_ARG;
+  if (n == 0) return MHD_OK;
   for (int i = 0; i < n; ++i)
     if (!ctxs[i] || nsteps[i] < 0) return MHD_ERR_INVALID_ARG;
-  for (int i = 0; i < n; ++i) {
-    hipStream_t keep = ctxs[i]->stream;
-    if (stream) ctxs[i]->stream = (hipStream_t)stream;
-    int rc = mhd_step(ctxs[i], nsteps[i], 0.0);
-    ctxs[i]->stream = keep;
-    if (rc) return rc;
+  const mhd_ctx* c0 = ctxs[0];
+  for (int i = 1; i < n; ++i) {
+    const mhd_ctx* c = ctxs[i];
+    if (c->p.precision != c0->p.precision || c->p.riemann != c0->p.riemann ||
+        c->p.integrator != c0->p.integrator || c->tile != c0->tile || c->device != c0->device)
+      return MHD_ERR_UNSUPPORTED;
   }
-  return MHD_OK;
+  hipStream_t st = stream ? (hipStream_t)stream : c0->stream;
+  return step_group(ctxs, nsteps, n, nullptr, st);
 }
 
 int mhd_destroy(mhd_ctx* c) {

@@ -51,21 +51,33 @@ __device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
 // Tile variants of the stage kernel.
 enum { TILE_16x16 = 1, TILE_24x8 = 2 };
 
-struct StageLaunch {
-  void* src[8];
-  void* dst[8];
+// One box as the stage kernel sees it; each context keeps its descriptor in its
+// own workspace (written once when the context is created).
+struct BoxDesc {
+  void* buf[2][8];        // two state buffers: rho mx my mz en bx by bz
   int nx, ny, nz;
-  int lz;
-  double idl[3];
+  int ntx, nty, nzc, lz;  // tiles of the context's tile shape, z-chunks
+  int pad;
+  double idl[3];          // 1 / dl_d
   double gamma;
   Scalars* sc;
-  int tile, solver, mode;
+};
+
+// One stage launch over up to kMaxBatch boxes: global block g belongs to the
+// box b with start[b] <= g < start[b + 1]; src[b] is the buffer it reads
+// (it writes the other one).
+constexpr int kMaxBatch = 64;
+struct BatchArgs {
+  int nbox, mode, total;
+  int pad;
+  const BoxDesc* desc[kMaxBatch];
+  int start[kMaxBatch + 1];
+  unsigned char src[kMaxBatch];
 };
 
 // stage launch for one precision (mhd_stage_f64.hip / mhd_stage_f32.hip)
-hipError_t stage_f64(const StageLaunch& l, hipStream_t st, bool prepare);
-hipError_t stage_f32(const StageLaunch& l, hipStream_t st, bool prepare);
-int stage_blocks(int tile, int nx, int ny, int nz, int lz);
+hipError_t stage_f64(const BatchArgs& b, int tile, int solver, hipStream_t st, bool prepare);
+hipError_t stage_f32(const BatchArgs& b, int tile, int solver, hipStream_t st, bool prepare);
 int tile_dims(int tile, int* tx, int* ty);
 
 }  // namespace mhd

@@ -27,14 +27,13 @@
 
 namespace mhd {
 
-// Arguments of one stage launch.
+// One box's view inside a stage launch.
 template <typename R>
 struct StageArgs {
   const R* src[8];  // state the operator acts on: rho mx my mz en bx by bz
   R* dst[8];        // output state (second RK2 stage: also holds U_0)
   int nx, ny, nz;
   int ntx, nty, nzc, lz;  // tiles in x, y; z-chunks and their length
-  int nblocks;
   R idl[3];  // 1 / dl_d
   R gamma, gm1, igm1;
   const Scalars* sc;  // device scalars: dt of this cycle, CFL maximum, status
@@ -42,6 +41,17 @@ struct StageArgs {
 };
 
 enum { MODE_STAGE1 = 0, MODE_STAGE2 = 1, MODE_MEASURE = 2 };
+
+// State arrays live in global memory; loads and stores through these helpers
+// use global (not flat) instructions.
+template <typename R>
+__device__ __forceinline__ R gld(const R* p, long long o) {
+  return ((const __attribute__((address_space(1))) R*)p)[o];
+}
+template <typename R>
+__device__ __forceinline__ void gst(R* p, long long o, R v) {
+  ((__attribute__((address_space(1))) R*)p)[o] = v;
+}
 
 __device__ __forceinline__ int wrapi(int i, int n) {
   i %= n;
@@ -96,17 +106,17 @@ __device__ __forceinline__ void load_raw(const StageArgs<R>& a, int gi, int gi1,
                                          int gk, int gk1, Raw<R>& r) {
   const long long plane = (long long)a.nx * a.ny;
   const long long o = (long long)gk * plane + (long long)gj * a.nx + gi;
-  r.rho = a.src[0][o];
-  r.mx = a.src[1][o];
-  r.my = a.src[2][o];
-  r.mz = a.src[3][o];
-  r.en = a.src[4][o];
-  r.bxl = a.src[5][o];
-  r.bxr = a.src[5][o - gi + gi1];
-  r.byl = a.src[6][o];
-  r.byr = a.src[6][o + (long long)(gj1 - gj) * a.nx];
-  r.bzl = a.src[7][o];
-  r.bzr = a.src[7][o + (long long)(gk1 - gk) * plane];
+  r.rho = gld(a.src[0], o);
+  r.mx = gld(a.src[1], o);
+  r.my = gld(a.src[2], o);
+  r.mz = gld(a.src[3], o);
+  r.en = gld(a.src[4], o);
+  r.bxl = gld(a.src[5], o);
+  r.bxr = gld(a.src[5], o - gi + gi1);
+  r.byl = gld(a.src[6], o);
+  r.byr = gld(a.src[6], o + (long long)(gj1 - gj) * a.nx);
+  r.bzl = gld(a.src[7], o);
+  r.bzr = gld(a.src[7], o + (long long)(gk1 - gk) * plane);
 }
 
 // Face-frame primitive of a cell for direction d (cyclic tangents).
@@ -224,7 +234,7 @@ struct Carry {
   static constexpr bool in_lds = sizeof(R) == 8 && TX == 16;
   static constexpr int NT = Tile<TX, TY>::NT;
   static constexpr int N = in_lds ? NT : 1;
-  R part[5][N], fzp[5][N], um[5][N];
+  R part[5][N], fzp[5][N];
 };
 
 template <typename R, int TX, int TY>
@@ -249,7 +259,7 @@ struct Occupancy {
 template <typename R, int SOLVER, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY + 2 * (TX + TY))
 __attribute__((amdgpu_waves_per_eu(Occupancy<R>::waves)))
-stage_kernel(StageArgs<R> a) {
+stage_kernel(BatchArgs ba) {
   using T = Tile<TX, TY>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   SmemAll<R, TX, TY>& SA = *reinterpret_cast<SmemAll<R, TX, TY>*>(smem_raw);
@@ -260,9 +270,30 @@ stage_kernel(StageArgs<R> a) {
   // each XCD a contiguous run of spatially adjacent tiles so halos hit its L2.
   int b = blockIdx.x;
   {
-    const int q = a.nblocks / 8, rr = a.nblocks % 8;
+    const int q = ba.total / 8, rr = ba.total % 8;
     const int x = b % 8, s = b / 8;
     b = (x < rr ? x * (q + 1) : rr * (q + 1) + (x - rr) * q) + s;
+  }
+  // the box this tile belongs to (uniform per block)
+  int box = 0;
+  while (box + 1 < ba.nbox && ba.start[box + 1] <= b) ++box;
+  b -= ba.start[box];
+  StageArgs<R> a;
+  {
+    const BoxDesc* d = ba.desc[box];
+    const int si = ba.src[box];
+    for (int f = 0; f < 8; ++f) {
+      a.src[f] = static_cast<const R*>(d->buf[si][f]);
+      a.dst[f] = static_cast<R*>(d->buf[1 - si][f]);
+    }
+    a.nx = d->nx; a.ny = d->ny; a.nz = d->nz;
+    a.ntx = d->ntx; a.nty = d->nty; a.nzc = d->nzc; a.lz = d->lz;
+    for (int k = 0; k < 3; ++k) a.idl[k] = (R)d->idl[k];
+    a.gamma = (R)d->gamma;
+    a.gm1 = (R)(d->gamma - 1.0);
+    a.igm1 = (R)(1.0 / (d->gamma - 1.0));
+    a.sc = d->sc;
+    a.scw = d->sc;
   }
   const int tx = b % a.ntx;
   const int ty = (b / a.ntx) % a.nty;
@@ -276,6 +307,8 @@ stage_kernel(StageArgs<R> a) {
   T::column(t, ci, cj);
   const int gi = wrapi(x0 + ci, a.nx), gj = wrapi(y0 + cj, a.ny);
   const int gi1 = wrapi(gi + 1, a.nx), gj1 = wrapi(gj + 1, a.ny);
+  const long long plane = (long long)a.nx * a.ny;
+  const long long col = (long long)gj * a.nx + gi;  // own column within a plane
   const bool interior = ci >= 0 && ci < TX && cj >= 0 && cj < TY;
   const bool real = interior && (x0 + ci < a.nx) && (y0 + cj < a.ny);
   const bool left = ci == -1, right = ci == TX, bottom = cj == -1, top = cj == TY;
@@ -303,16 +336,15 @@ stage_kernel(StageArgs<R> a) {
   const R tau_x = dt * a.idl[0], tau_y = dt * a.idl[1], tau_z = dt * a.idl[2];
 
   // ---- registers carried along the march
-  Cell<R> wm1, w0;     // primitives of planes m-1 and m (own column)
-  R top7[7];           // z-face left state from the top of cell m-1
-  R bx_m = 0, by_m = 0, bz_m = 0;     // face B of plane m (own column)
-  R bx_p = 0, by_p = 0;                // face B of plane m-1
-  // conserved of plane m (own column), U - tau_x dFx - tau_y dFy of cell m-1 and
-  // the z-flux at (m-1)-1/2: registers, or this thread's LDS slots
-  R u_m[5] = {0, 0, 0, 0, 0};
+  // z-window of the own column: the z-frame primitives of plane m-1 (plane m
+  // is read back from the LDS plane) and the z-face left state from the top of
+  // cell m-1
+  R zm1[7];
+  R top7[7];
+  // U - tau_x dFx - tau_y dFy of cell m-1 and the z-flux at (m-1)-1/2:
+  // registers, or this thread's LDS slots
   R part[5] = {0, 0, 0, 0, 0};
   R fz_prev[5] = {0, 0, 0, 0, 0};
-  auto um = [&](int q) -> R& { if constexpr (CL) return SA.c.um[q][t]; else return u_m[q]; };
   auto pt_ = [&](int q) -> R& { if constexpr (CL) return SA.c.part[q][t]; else return part[q]; };
   auto fzp = [&](int q) -> R& { if constexpr (CL) return SA.c.fzp[q][t]; else return fz_prev[q]; };
   R zc_prev = 0;                       // its signal speed
@@ -330,12 +362,12 @@ stage_kernel(StageArgs<R> a) {
     Raw<R> r;
     int k = wrapi(z0 - 2, a.nz);
     load_raw(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
-    to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, wm1);
+    Cell<R> w0;
+    to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w0);
+    frame_vals<2>(w0, zm1);
     k = wrapi(z0 - 1, a.nz);
     load_raw(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
     to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w0);
-    bx_m = r.bxl; by_m = r.byl; bz_m = r.bzl;
-    um(0) = r.rho; um(1) = r.mx; um(2) = r.my; um(3) = r.mz; um(4) = r.en;
     const int iw = T::w(ci, cj);
     S.w[0][iw] = w0.rho; S.w[1][iw] = w0.vx; S.w[2][iw] = w0.vy; S.w[3][iw] = w0.vz;
     S.w[4][iw] = w0.bx; S.w[5][iw] = w0.by; S.w[6][iw] = w0.bz; S.w[7][iw] = w0.p;
@@ -379,9 +411,9 @@ stage_kernel(StageArgs<R> a) {
       if (corner_x) {
         const long long o = (long long)km * a.nx * a.ny + (long long)wrapi(y0 - 1, a.ny) * a.nx +
                             wrapi(x0 + TX, a.nx);
-        bn = a.src[5][o];
+        bn = gld(a.src[5], o);
       } else {
-        bn = bx_m;
+        bn = gld(a.src[5], (long long)km * plane + col);
       }
       solve_face<0, SOLVER>(a, ql, qr, bn, fx);
       // the previous plane's exports were consumed before the last barrier
@@ -420,9 +452,9 @@ stage_kernel(StageArgs<R> a) {
       if (corner_y) {
         const long long o = (long long)km * a.nx * a.ny + (long long)wrapi(y0 + TY, a.ny) * a.nx +
                             wrapi(x0 - 1, a.nx);
-        bn = a.src[6][o];
+        bn = gld(a.src[6], o);
       } else {
-        bn = by_m;
+        bn = gld(a.src[6], (long long)km * plane + col);
       }
       solve_face<1, SOLVER>(a, ql, qr, bn, fy);
       if (corner_y) {
@@ -443,15 +475,20 @@ stage_kernel(StageArgs<R> a) {
 
     // ---------------- next plane's primitives and the z-face at m-1/2
     Cell<R> w1;
-    R bx_n, by_n, bz_n, u_n[5];
     {
       Raw<R> r;
       const int kn = wrapi(m + 1, a.nz);
       load_raw(a, gi, gi1, gj, gj1, kn, wrapi(kn + 1, a.nz), r);
       to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w1);
-      bx_n = r.bxl; by_n = r.byl; bz_n = r.bzl;
-      u_n[0] = r.rho; u_n[1] = r.mx; u_n[2] = r.my; u_n[3] = r.mz; u_n[4] = r.en;
     }
+    // own primitives of plane m, still in the LDS plane
+    Cell<R> w0;
+    {
+      const int iw = T::w(ci, cj);
+      w0.rho = S.w[0][iw]; w0.vx = S.w[1][iw]; w0.vy = S.w[2][iw]; w0.vz = S.w[3][iw];
+      w0.bx = S.w[4][iw]; w0.by = S.w[5][iw]; w0.bz = S.w[6][iw]; w0.p = S.w[7][iw];
+    }
+    const R bz_m = gld(a.src[7], (long long)km * plane + col);
     Cell<R> wx;  // halo item of plane m+1
     if (has_extra) {
       Raw<R> r;
@@ -462,7 +499,8 @@ stage_kernel(StageArgs<R> a) {
     Face<R> fz = {};
     {
       R qa[7], qb[7], qc[7];
-      frame_vals<2>(wm1, qa);
+#pragma unroll
+      for (int v = 0; v < 7; ++v) qa[v] = zm1[v];
       frame_vals<2>(w0, qb);
       frame_vals<2>(w1, qc);
       R bot[7];
@@ -474,7 +512,10 @@ stage_kernel(StageArgs<R> a) {
       }
       if (m >= z0) solve_face<2, SOLVER>(a, top7, bot, bz_m, fz);
 #pragma unroll
-      for (int v = 0; v < 7; ++v) top7[v] = qa[v];
+      for (int v = 0; v < 7; ++v) {
+        top7[v] = qa[v];
+        zm1[v] = qb[v];  // z-window shifts to plane m
+      }
     }
     // own cell EMFs of plane m: -(v x B)
     const R erx = w0.vz * w0.by - w0.vy * w0.bz;
@@ -532,7 +573,7 @@ stage_kernel(StageArgs<R> a) {
       const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
 #pragma unroll
       for (int q = 0; q < 5; ++q)
-        part_new[q] = (um(q) - tau_x * (S.xcons[q][e_e] - S.xcons[q][ex_me])) -
+        part_new[q] = (gld(a.src[q], (long long)km * plane + col) - tau_x * (S.xcons[q][e_e] - S.xcons[q][ex_me])) -
                       tau_y * (S.ycons[q][e_n] - S.ycons[q][ex_me]);
       if constexpr (MODE != MODE_STAGE2) {
         R cx = S.xcmax[ex_me] > S.xcmax[e_e] ? S.xcmax[ex_me] : S.xcmax[e_e];
@@ -541,9 +582,8 @@ stage_kernel(StageArgs<R> a) {
       }
     }
     // finalise cell m-1: z-flux difference, stage combination, face B
-    const long long plane = (long long)a.nx * a.ny;
     if (real && m - 1 >= z0 && m <= z1) {
-      const long long o = (long long)wrapi(m - 1, a.nz) * plane + (long long)gj * a.nx + gi;
+      const long long o = (long long)wrapi(m - 1, a.nz) * plane + col;
       if constexpr (MODE != MODE_STAGE2) {
         R cz = zc_prev > fz.cmax ? zc_prev : fz.cmax;
         R inv = cxy_prev + cz * a.idl[2];
@@ -554,18 +594,18 @@ stage_kernel(StageArgs<R> a) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) un[q] = pt_(q) - tau_z * (fz.cons[q] - fzp(q));
         const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
-        R bxn = (bx_p - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
-        R byn = (by_p - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
+        R bxn = (gld(a.src[5], o) - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
+        R byn = (gld(a.src[6], o) - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
         if constexpr (MODE == MODE_STAGE2) {
 #pragma unroll
-          for (int q = 0; q < 5; ++q) un[q] = R(0.5) * un[q] + R(0.5) * a.dst[q][o];
-          bxn = R(0.5) * bxn + R(0.5) * a.dst[5][o];
-          byn = R(0.5) * byn + R(0.5) * a.dst[6][o];
+          for (int q = 0; q < 5; ++q) un[q] = R(0.5) * un[q] + R(0.5) * gld<R>(a.dst[q], o);
+          bxn = R(0.5) * bxn + R(0.5) * gld<R>(a.dst[5], o);
+          byn = R(0.5) * byn + R(0.5) * gld<R>(a.dst[6], o);
         }
 #pragma unroll
-        for (int q = 0; q < 5; ++q) a.dst[q][o] = un[q];
-        a.dst[5][o] = bxn;
-        a.dst[6][o] = byn;
+        for (int q = 0; q < 5; ++q) gst(a.dst[q], o, un[q]);
+        gst(a.dst[5], o, bxn);
+        gst(a.dst[6], o, byn);
       }
     }
     __syncthreads();  // reads of corner-EMF buffers of plane m-1 done
@@ -577,11 +617,11 @@ stage_kernel(StageArgs<R> a) {
     __syncthreads();
     if constexpr (MODE != MODE_MEASURE) {
       if (real && m >= z0 && m < z1) {
-        const long long o = (long long)km * plane + (long long)gj * a.nx + gi;
+        const long long o = (long long)km * plane + col;
         const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
         R bzn = (bz_m - tau_x * (S.ey[e_e] - ey_new)) + tau_y * (S.ex[e_n] - ex_new);
-        if constexpr (MODE == MODE_STAGE2) bzn = R(0.5) * bzn + R(0.5) * a.dst[7][o];
-        a.dst[7][o] = bzn;
+        if constexpr (MODE == MODE_STAGE2) bzn = R(0.5) * bzn + R(0.5) * gld<R>(a.dst[7], o);
+        gst(a.dst[7], o, bzn);
       }
     }
 
@@ -590,7 +630,6 @@ stage_kernel(StageArgs<R> a) {
     for (int q = 0; q < 5; ++q) {
       pt_(q) = part_new[q];
       fzp(q) = fz.cons[q];
-      um(q) = u_n[q];
     }
     zc_prev = fz.cmax;
     cxy_prev = cxy_new;
@@ -602,10 +641,6 @@ stage_kernel(StageArgs<R> a) {
     ery_prev = ery;
     ex_prev = ex_new;
     ey_prev = ey_new;
-    bx_p = bx_m; by_p = by_m;
-    bx_m = bx_n; by_m = by_n; bz_m = bz_n;
-    wm1 = w0;
-    w0 = w1;
     if (extra_corner) erz_extra = wx.vy * wx.bx - wx.vx * wx.by;
     // the LDS plane now holds plane m+1 (written in B)
   }
@@ -629,35 +664,36 @@ stage_kernel(StageArgs<R> a) {
 // Launch one instantiation.  With prepare = true only raise its dynamic-LDS
 // limit (a host-side attribute, done once when a context is created).
 template <typename R, int SOLVER, int MODE, int TX, int TY>
-static hipError_t launch_one(const StageArgs<R>& a, hipStream_t st, bool prepare) {
+static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) {
   using T = Tile<TX, TY>;
   const size_t lds = sizeof(SmemAll<R, TX, TY>);
   auto fn = stage_kernel<R, SOLVER, MODE, TX, TY>;
   if (prepare)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(fn, dim3(a.nblocks), dim3(T::NT), lds, st, a);
+  hipLaunchKernelGGL(fn, dim3(ba.total), dim3(T::NT), lds, st, ba);
   return hipGetLastError();
 }
 
 template <typename R, int TX, int TY>
-static hipError_t launch_tile(const StageArgs<R>& a, int solver, int mode, hipStream_t st,
-                              bool prepare) {
+static hipError_t launch_tile(const BatchArgs& ba, int solver, hipStream_t st, bool prepare) {
+  const int mode = ba.mode;
   if (solver == 0) {
-    if (mode == MODE_STAGE1) return launch_one<R, 0, MODE_STAGE1, TX, TY>(a, st, prepare);
-    if (mode == MODE_STAGE2) return launch_one<R, 0, MODE_STAGE2, TX, TY>(a, st, prepare);
-    return launch_one<R, 0, MODE_MEASURE, TX, TY>(a, st, prepare);
+    if (mode == MODE_STAGE1) return launch_one<R, 0, MODE_STAGE1, TX, TY>(ba, st, prepare);
+    if (mode == MODE_STAGE2) return launch_one<R, 0, MODE_STAGE2, TX, TY>(ba, st, prepare);
+    return launch_one<R, 0, MODE_MEASURE, TX, TY>(ba, st, prepare);
   }
-  if (mode == MODE_STAGE1) return launch_one<R, 1, MODE_STAGE1, TX, TY>(a, st, prepare);
-  if (mode == MODE_STAGE2) return launch_one<R, 1, MODE_STAGE2, TX, TY>(a, st, prepare);
-  return launch_one<R, 1, MODE_MEASURE, TX, TY>(a, st, prepare);
+  if (mode == MODE_STAGE1) return launch_one<R, 1, MODE_STAGE1, TX, TY>(ba, st, prepare);
+  if (mode == MODE_STAGE2) return launch_one<R, 1, MODE_STAGE2, TX, TY>(ba, st, prepare);
+  return launch_one<R, 1, MODE_MEASURE, TX, TY>(ba, st, prepare);
 }
 
 template <typename R, int TX, int TY>
 static hipError_t prepare_tile(int solver) {
-  StageArgs<R> a = {};
+  BatchArgs ba = {};
   for (int mode = 0; mode < 3; ++mode) {
-    hipError_t e = launch_tile<R, TX, TY>(a, solver, mode, nullptr, true);
+    ba.mode = mode;
+    hipError_t e = launch_tile<R, TX, TY>(ba, solver, nullptr, true);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -2,7 +2,7 @@
 #include "mhd_stage.inl"
 #include "mhd_stage_launch.inl"
 namespace mhd {
-hipError_t stage_f32(const StageLaunch& l, hipStream_t st, bool prepare) {
-  return stage_launch<float>(l, st, prepare);
+hipError_t stage_f32(const BatchArgs& b, int tile, int solver, hipStream_t st, bool prepare) {
+  return stage_launch<float>(b, tile, solver, st, prepare);
 }
 }  // namespace mhd

@@ -2,7 +2,7 @@
 #include "mhd_stage.inl"
 #include "mhd_stage_launch.inl"
 namespace mhd {
-hipError_t stage_f64(const StageLaunch& l, hipStream_t st, bool prepare) {
-  return stage_launch<double>(l, st, prepare);
+hipError_t stage_f64(const BatchArgs& b, int tile, int solver, hipStream_t st, bool prepare) {
+  return stage_launch<double>(b, tile, solver, st, prepare);
 }
 }  // namespace mhd
