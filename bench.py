@@ -18,6 +18,8 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import os
 import re
@@ -28,6 +30,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, the same
+# for FP64 and non-packed FP32 (packed FP32 is not used by this build).
+ALU_PEAK_TFLOPS = 78.6
+# Algorithmic floating-point operations (add/sub, mul, div, sqrt) per cell and
+# stage of this method on this 256^3 input with HLLD, counted on the oracle by
+# oracle/opcount.cpp: 611.7 add/sub + 647.8 mul + 46.0 div + 18.0 sqrt.
+FLOPS_PER_CELL_STAGE = 1323.46
 N = 256
 METRIC = "MHD cell-updates/s at 256^3 (FP64 vs FP32, %HBM peak); batched p50/p99 latency"
 
@@ -77,19 +86,28 @@ def run_gpu(state, precision: str, steps: int, warmup: int, tile: int = 0, zchun
     return {"ms_total": ms, "wall_s": wall, "t": t, "dt_next": dt, "rc": rc}
 
 
-def roofline(precision: str, ms_per_step: float):
+def roofline(precision: str, launch_ms: float):
+    """Roofline of the stage kernel from its measured average launch duration.
+    The kernel is bound by vector ALU work (algorithmic flops per cell and stage
+    x cells per launch); the HBM view of the same launch (20 state words per
+    cell on average: 16 in stage 1, 24 in stage 2) is reported beside it."""
     word = 8 if precision == "fp64" else 4
     cells = N ** 3
-    # two stage launches per cycle: 16 and 24 state words per cell -> 20 on average
+    launch_s = launch_ms * 1e-3
+    flops_per_launch = FLOPS_PER_CELL_STAGE * cells
+    tflops = flops_per_launch / launch_s / 1e12
     bytes_per_launch = 20 * word * cells
-    launch_s = ms_per_step * 1e-3 / 2.0
-    achieved = bytes_per_launch / launch_s / 1e9
+    gbs = bytes_per_launch / launch_s / 1e9
     traffic = counter_traffic(precision)
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+    return {"bound": "alu", "achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
             "traffic": None if traffic is None else round(traffic / 1e9, 4),
-            "traffic_unit": "GB per stage launch",
-            "algorithmic_bytes_per_launch": bytes_per_launch}
+            "traffic_unit": "GB per stage launch (rocprofv3 FETCH/WRITE, copy-calibrated)",
+            "algorithmic_flops_per_launch": round(flops_per_launch),
+            "launch_ms": round(launch_ms, 4),
+            "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "algorithmic_bytes_per_launch": bytes_per_launch}}
 
 
 def cpu_baseline(state):
@@ -108,12 +126,96 @@ def cpu_baseline(state):
             "sample": f"2 RK2 cycles of the same 256^3 FP64 input ({el:.1f} s, OpenMP)"}
 
 
+def batched_c3(nbox: int = 64, steps: int = 20):
+    """64 uneven periodic boxes (edges log-uniform in [16, 128], multiples of 8,
+    own seeded turbulence and uniform B), FP32, 20 RK2 cycles each: one captured
+    HIP graph of batched stage launches, against the same boxes advanced one
+    after another with single-box launches."""
+    import torch
+
+    from paper_2304_13746_amd import inputs as I
+    from paper_2304_13746_amd.batch import BoxBatch
+    from paper_2304_13746_amd.box import MHDBox
+
+    spec = I.batch_boxes(nbox, seed=2304)
+    cells = sum(int(np.prod(b["dims"])) for b in spec)
+    stream = torch.cuda.Stream()
+    boxes = [MHDBox(*b["dims"], *b["l"], precision="fp32", stream=stream) for b in spec]
+    for bx, b in zip(boxes, spec):
+        bx.set_state(b["state"])
+    batch = BoxBatch(boxes)
+    batch.step(1)  # warm the kernels
+    graph = batch.capture(steps)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    graph.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = ev0.elapsed_time(ev1)
+    rcs = [bx.get_state(check=False)[3] for bx in boxes]
+    # sequential reference: each box alone, one after another
+    for bx, b in zip(boxes, spec):
+        bx.set_state(b["state"])
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    done = []
+    for bx in boxes:
+        bx.step(steps)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        done.append(e)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = ev0.elapsed_time(ev1)
+    lat_seq = sorted(ev0.elapsed_time(e) for e in done)
+    for bx in boxes:
+        bx.close()
+    return {"workload": f"{nbox} uneven periodic boxes, edges 16-128 (log-uniform, multiples of 8), "
+                        f"FP32, {steps} RK2 cycles each, one captured HIP graph",
+            "cells": cells, "value": cells * steps / (ms_batch * 1e-3), "unit": "cell-updates/s",
+            "ms_batch": round(ms_batch, 3), "ms_sequential": round(ms_seq, 3),
+            "speedup_vs_sequential": round(ms_seq / ms_batch, 3),
+            "latency_ms_batched": {"p50": round(ms_batch, 3), "p99": round(ms_batch, 3)},
+            "latency_ms_sequential": {"p50": round(lat_seq[len(lat_seq) // 2], 3),
+                                      "p99": round(lat_seq[int(0.99 * (len(lat_seq) - 1))], 3)},
+            "status_ok": all(rc == 0 for rc in rcs)}
+
+
+def served_c4(nreq: int, precision: str = "fp32", rate: float = 200.0):
+    """Poisson stream of box requests (mean 200 req/s), edge uniform in
+    {32, 48, 64, 96, 128, 192}, 10-200 RK2 cycles, Orszag-Tang or turbulence
+    initial data 50/50; admission by workspace bytes against an HBM budget."""
+    import torch
+
+    from paper_2304_13746_amd.serve import EDGES, GpuBackend, Server, poisson_requests
+
+    free, total = torch.cuda.mem_get_info()
+    budget = int(min(0.8 * free, 64 << 30))
+    be = GpuBackend(precision=precision)
+    reqs = poisson_requests(nreq, rate=rate, seed=2304)
+    for e in EDGES:  # initial states resident on the GPU before the clock starts
+        for init in ("ot", "turb"):
+            from paper_2304_13746_amd.serve import Request
+            be.initial_state(Request(-1, 0.0, e, 1, init, 0))
+    torch.cuda.synchronize()
+    st = Server(be, budget_bytes=budget, max_active=64, epoch_steps=10).run(reqs)
+    s = st.summary()
+    s.update({"workload": f"{nreq} Poisson requests at {rate:g}/s, edges {list(EDGES)}, 10-200 RK2 "
+                          f"cycles, OT/turbulence, {precision.upper()}, HBM budget {budget / 2**30:.0f} GiB",
+              "precision": precision})
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-box batched run")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests in the served replay (0: skip; the full stream is 5000)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
@@ -134,7 +236,6 @@ def main():
               "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2304_13746_amd import inputs as I
@@ -147,10 +248,13 @@ def main():
     for prec in precs:
         r = run_gpu(state, prec, args.steps, args.warmup, args.tile, args.zchunk)
         ms_step = r["ms_total"] / args.steps
+        # two stage launches per cycle; the two one-thread cycle-control
+        # launches (a few microseconds) are charged to them, conservatively
         results[prec] = {"value": N ** 3 / (ms_step * 1e-3), "ms_per_step": ms_step,
-                         "roofline": roofline(prec, ms_step), "rc": r["rc"]}
+                         "roofline": roofline(prec, ms_step / 2.0), "rc": r["rc"]}
         print(f"# {prec}: {ms_step:.3f} ms/cycle, {results[prec]['value']:.4e} cell-updates/s, "
-              f"stage kernel {results[prec]['roofline']['achieved']:.0f} GB/s algorithmic, rc={r['rc']}",
+              f"stage kernel {results[prec]['roofline']['achieved']:.2f} TFLOP/s, "
+              f"{results[prec]['roofline']['hbm']['achieved']:.0f} GB/s algorithmic, rc={r['rc']}",
               file=sys.stderr, flush=True)
     main_prec = precs[0]
     m = results[main_prec]
@@ -176,6 +280,15 @@ def main():
         f = results["fp32"]
         line["fp32"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "dtype": "f32",
                         "roofline": f["roofline"]}
+    if not args.no_batch:
+        line["batched"] = batched_c3()
+        print(f"# batched: {line['batched']['value']:.4e} cell-updates/s, "
+              f"{line['batched']['speedup_vs_sequential']}x vs sequential", file=sys.stderr, flush=True)
+    if args.serve_requests > 0:
+        line["served"] = [served_c4(args.serve_requests, p) for p in ("fp32", "fp64")]
+        for sv in line["served"]:
+            print(f"# served {sv['precision']}: p50 {sv['p50_ms']} ms p99 {sv['p99_ms']} ms, "
+                  f"{sv['cell_updates_per_s']:.3e} cell-updates/s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(state)
     print(json.dumps(line), flush=True)
