@@ -56,6 +56,10 @@ typedef enum { MHD_RK2 = 0, MHD_EULER = 1 } mhd_integrator;   /* Tab. weights */
 
 typedef struct mhd_ctx mhd_ctx; /* opaque */
 
+/* Stage-kernel tile: the x-by-y column block one work-group owns (plus a
+ * one-cell ring).  Results do not depend on it (bit-identical in FP64). */
+enum { MHD_TILE_DEFAULT = 0, MHD_TILE_16x16 = 1, MHD_TILE_24x8 = 2 };
+
 typedef struct {
   int nx, ny, nz;         /* cells per direction, each in [1, 4096] */
   double lx, ly, lz;      /* box lengths > 0; cell size dl_d = l_d / n_d */
@@ -68,7 +72,7 @@ typedef struct {
   void* workspace;        /* device pointer, 256-byte aligned, BORROWED */
   size_t workspace_bytes; /* >= mhd_workspace_bytes(this) */
   void* stream;           /* hipStream_t to enqueue on (NULL: default stream) */
-  int tile;               /* kernel tile variant, 0 = default for the precision */
+  int tile;               /* MHD_TILE_*, 0 = default (24x8) */
   int zchunk;             /* z-planes per thread block, 0 = automatic */
 } mhd_params;
 
@@ -127,6 +131,36 @@ int mhd_get_diagnostics(mhd_ctx* ctx, mhd_diag* out);
  * synchronised with: order them against the batch stream first.  Asynchronous,
  * allocation-free, capture-safe. */
 int mhd_step_batch(mhd_ctx* const* ctxs, const int* nsteps, int n, void* stream);
+
+/* Launch shape of a context: tile (MHD_TILE_*) and z-planes per work-group
+ * (zchunk >= 0, 0 = automatic, values above nz mean nz).  Changing it changes
+ * only how the work is split: FP64 results are bit-identical for every shape.
+ * mhd_set_launch synchronises the context's stream; it must not be called while
+ * a captured graph that contains this context is still to be replayed (the
+ * graph keeps the launch grid it was captured with).  mhd_get_launch returns
+ * the tile and the z-planes per work-group in effect (either pointer may be
+ * NULL). */
+int mhd_set_launch(mhd_ctx* ctx, int tile, int zchunk);
+int mhd_get_launch(const mhd_ctx* ctx, int* tile, int* zchunk);
+
+typedef struct {
+  int tile;          /* chosen tile (MHD_TILE_*) */
+  int zchunk_cap;    /* chosen cap on z-planes per work-group (0 = automatic) */
+  float best_ms;     /* median duration of one stage launch with that shape */
+  float default_ms;  /* the same for the default shape */
+  int candidates;    /* shapes timed */
+} mhd_tune_result;
+
+/* Autotuner: time the first-stage launch of the whole group (one batched launch,
+ * as mhd_step_batch issues it) for every tile and every z-chunk cap in
+ * {automatic, 8, 16, 32, 64, 128}, reps >= 1 times each after one warm-up, on
+ * stream (NULL: the stream of ctxs[0]); then give every context the fastest
+ * shape (tile, min(cap, nz)).  The first-stage launch reads the current state
+ * and writes only the second buffer and the CFL maximum of the cycle being
+ * prepared, so the state, t and the next step are unchanged.  Contexts must
+ * share device, precision, solver, integrator and tile (as mhd_step_batch).
+ * Synchronises; out may be NULL. */
+int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_result* out);
 
 /* Release the context (not the borrowed workspace).  Safe on NULL. */
 int mhd_destroy(mhd_ctx* ctx);

@@ -26,7 +26,8 @@ MHD_RK2, MHD_EULER = 0, 1
 TILE_16x16, TILE_24x8 = 1, 2
 
 EXPORTED = ("mhd_workspace_bytes", "mhd_create", "mhd_set_state", "mhd_step", "mhd_get_state",
-            "mhd_get_diagnostics", "mhd_step_batch", "mhd_destroy", "mhd_status_string")
+            "mhd_get_diagnostics", "mhd_step_batch", "mhd_set_launch", "mhd_get_launch", "mhd_tune",
+            "mhd_destroy", "mhd_status_string")
 
 
 class Params(C.Structure):
@@ -47,6 +48,11 @@ class Diag(C.Structure):
     _fields_ = [("mass", C.c_double), ("mom", C.c_double * 3), ("energy", C.c_double),
                 ("bflux", C.c_double * 3), ("divb_max", C.c_double), ("divb_rms", C.c_double),
                 ("status", C.c_uint)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("tile", C.c_int), ("zchunk_cap", C.c_int), ("best_ms", C.c_float),
+                ("default_ms", C.c_float), ("candidates", C.c_int)]
 
 
 class MHDError(RuntimeError):
@@ -75,6 +81,9 @@ def lib():
         L.mhd_get_state.argtypes = [C.c_void_p, P(StateView), P(C.c_double), P(C.c_double)]
         L.mhd_get_diagnostics.argtypes = [C.c_void_p, P(Diag)]
         L.mhd_step_batch.argtypes = [P(C.c_void_p), P(C.c_int), C.c_int, C.c_void_p]
+        L.mhd_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.mhd_get_launch.argtypes = [C.c_void_p, P(C.c_int), P(C.c_int)]
+        L.mhd_tune.argtypes = [P(C.c_void_p), C.c_int, C.c_int, C.c_void_p, P(TuneResult)]
         L.mhd_destroy.argtypes = [C.c_void_p]
         L.mhd_status_string.argtypes = [C.c_int]
         L.mhd_status_string.restype = C.c_char_p

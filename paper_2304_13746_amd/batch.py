@@ -44,6 +44,13 @@ class BoxBatch:
                                         C.c_void_p(self.stream.cuda_stream)), "mhd_step_batch")
         return self
 
+    def tune(self, tuner=None, force: bool = False) -> dict:
+        """Choose one launch shape for the whole batch (autotune.Tuner: cached,
+        else timed on the GPU) and apply it to every box."""
+        from .autotune import Tuner
+        tuner = tuner or Tuner()
+        return tuner.tune(self.boxes, self.stream, force=force)
+
     def capture(self, nsteps) -> "StepGraph":
         """Record the launches of ``step(nsteps)`` into a HIP graph on the batch's
         stream (RK2 only: the buffer roles of an Euler cycle alternate on the

@@ -129,6 +129,19 @@ class MHDBox:
                 "bflux": np.array(d.bflux[:]), "divb_max": d.divb_max, "divb_rms": d.divb_rms,
                 "status": d.status}
 
+    # ---- launch shape
+
+    def set_launch(self, tile: int = 0, zchunk: int = 0):
+        """Tile (TILE_* constant, 0 = default) and z-planes per work-group
+        (0 = automatic).  Synchronises the box's stream."""
+        L.check(self.lib.mhd_set_launch(self.ctx, int(tile), int(zchunk)), "mhd_set_launch")
+        return self
+
+    def get_launch(self):
+        t, z = C.c_int(), C.c_int()
+        L.check(self.lib.mhd_get_launch(self.ctx, C.byref(t), C.byref(z)), "mhd_get_launch")
+        return t.value, z.value
+
     def close(self):
         if self.ctx:
             self.lib.mhd_destroy(self.ctx)

@@ -23,7 +23,8 @@ struct mhd_ctx {
   Scalars* sc;       // device scalars
   BoxDesc* desc;     // device copy of this box's descriptor
   double* diag_part; // per-block diagnostic partials
-  int tile, lz;
+  int tile, zchunk;  // launch shape as requested (zchunk 0 = automatic)
+  int lz;            // z-planes per work-group in effect
   int diag_blocks;
   int tiles;         // stage-kernel blocks for this box
 };
@@ -296,6 +297,53 @@ int choose_lz(int tile, int nx, int ny, int nz) {
   return lz;
 }
 
+
+// Give c the launch shape (tile, zchunk; 0 = automatic): raise the dynamic-LDS
+// limit of the tile's kernels and rewrite the box descriptor on the device.
+// Synchronous: kernels in flight on c's stream may still read the old one.
+int apply_shape(mhd_ctx* c, int tile, int zchunk) {
+  int tx, ty;
+  if (!tile_dims(tile, &tx, &ty)) return MHD_ERR_INVALID_ARG;
+  const mhd_params* p = &c->p;
+  BatchArgs none = {};
+  hipError_t e = p->precision == MHD_FP32 ? stage_f32(none, tile, p->riemann, nullptr, true)
+                                          : stage_f64(none, tile, p->riemann, nullptr, true);
+  if (e != hipSuccess) return MHD_ERR_HIP;
+  const int lz = zchunk > 0 ? (zchunk < p->nz ? zchunk : p->nz) : choose_lz(tile, p->nx, p->ny, p->nz);
+  BoxDesc d = {};
+  for (int b = 0; b < 2; ++b)
+    for (int f = 0; f < 8; ++f) d.buf[b][f] = c->buf[b][f];
+  d.nx = p->nx;
+  d.ny = p->ny;
+  d.nz = p->nz;
+  d.ntx = (p->nx + tx - 1) / tx;
+  d.nty = (p->ny + ty - 1) / ty;
+  d.lz = lz;
+  d.nzc = (p->nz + lz - 1) / lz;
+  for (int k = 0; k < 3; ++k) d.idl[k] = c->idl[k];
+  d.gamma = p->gamma;
+  d.sc = c->sc;
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess)
+    return MHD_ERR_HIP;
+  c->tile = tile;
+  c->zchunk = zchunk;
+  c->lz = lz;
+  c->tiles = d.ntx * d.nty * d.nzc;
+  return MHD_OK;
+}
+
+bool same_group(mhd_ctx* const* ctxs, int n) {
+  const mhd_ctx* c0 = ctxs[0];
+  for (int i = 1; i < n; ++i) {
+    const mhd_ctx* c = ctxs[i];
+    if (c->p.precision != c0->p.precision || c->p.riemann != c0->p.riemann ||
+        c->p.integrator != c0->p.integrator || c->tile != c0->tile || c->device != c0->device)
+      return false;
+  }
+  return true;
+}
+
 }  // namespace
 
 namespace mhd {
@@ -367,33 +415,8 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
       w += fb;
     }
   c->cur = 0;
-  c->tile = tile;
-  c->lz = p->zchunk > 0 ? (p->zchunk < p->nz ? p->zchunk : p->nz) : choose_lz(tile, p->nx, p->ny, p->nz);
   c->diag_blocks = kDiagBlocks;
-  // raise the dynamic-LDS limit of this tile's kernels (host-side attribute)
-  BatchArgs none = {};
-  hipError_t e = p->precision == MHD_FP32 ? stage_f32(none, tile, p->riemann, nullptr, true)
-                                          : stage_f64(none, tile, p->riemann, nullptr, true);
-  if (e != hipSuccess) {
-    free(c);
-    return MHD_ERR_HIP;
-  }
-  BoxDesc d = {};
-  for (int b = 0; b < 2; ++b)
-    for (int f = 0; f < 8; ++f) d.buf[b][f] = c->buf[b][f];
-  d.nx = p->nx;
-  d.ny = p->ny;
-  d.nz = p->nz;
-  d.ntx = (p->nx + tx - 1) / tx;
-  d.nty = (p->ny + ty - 1) / ty;
-  d.lz = c->lz;
-  d.nzc = (p->nz + c->lz - 1) / c->lz;
-  for (int k = 0; k < 3; ++k) d.idl[k] = c->idl[k];
-  d.gamma = p->gamma;
-  d.sc = c->sc;
-  c->tiles = d.ntx * d.nty * d.nzc;
-  if (hipMemcpyAsync(c->desc, &d, sizeof(d), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
+  if (apply_shape(c, tile, p->zchunk) != MHD_OK) {
     free(c);
     return MHD_ERR_HIP;
   }
@@ -495,15 +518,101 @@ int mhd_step_batch(mhd_ctx* const* ctxs, const int* nsteps, int n, void* stream)
   if (n == 0) return MHD_OK;
   for (int i = 0; i < n; ++i)
     if (!ctxs[i] || nsteps[i] < 0) return MHD_ERR_INVALID_ARG;
-  const mhd_ctx* c0 = ctxs[0];
-  for (int i = 1; i < n; ++i) {
-    const mhd_ctx* c = ctxs[i];
-    if (c->p.precision != c0->p.precision || c->p.riemann != c0->p.riemann ||
-        c->p.integrator != c0->p.integrator || c->tile != c0->tile || c->device != c0->device)
-      return MHD_ERR_UNSUPPORTED;
-  }
-  hipStream_t st = stream ? (hipStream_t)stream : c0->stream;
+  if (!same_group(ctxs, n)) return MHD_ERR_UNSUPPORTED;
+  hipStream_t st = stream ? (hipStream_t)stream : ctxs[0]->stream;
   return step_group(ctxs, nsteps, n, nullptr, st);
+}
+
+int mhd_set_launch(mhd_ctx* c, int tile, int zchunk) {
+  if (!c || zchunk < 0) return MHD_ERR_INVALID_ARG;
+  if (tile == MHD_TILE_DEFAULT) tile = default_tile(c->p.precision);
+  int tx, ty;
+  if (!tile_dims(tile, &tx, &ty)) return MHD_ERR_INVALID_ARG;
+  return apply_shape(c, tile, zchunk);
+}
+
+int mhd_get_launch(const mhd_ctx* c, int* tile, int* zchunk) {
+  if (!c) return MHD_ERR_INVALID_ARG;
+  if (tile) *tile = c->tile;
+  if (zchunk) *zchunk = c->lz;
+  return MHD_OK;
+}
+
+int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_result* out) {
+  if (!ctxs || n < 1 || n > 4096 || reps < 1 || reps > 100) return MHD_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return MHD_ERR_INVALID_ARG;
+  if (!same_group(ctxs, n)) return MHD_ERR_UNSUPPORTED;
+  hipStream_t st = stream ? (hipStream_t)stream : ctxs[0]->stream;
+  static const int tiles[] = {TILE_24x8, TILE_16x16};
+  static const int caps[] = {0, 8, 16, 32, 64, 128};
+  const int ntile = sizeof(tiles) / sizeof(tiles[0]), ncap = sizeof(caps) / sizeof(caps[0]);
+  int* src = (int*)malloc(sizeof(int) * n);
+  float* times = (float*)malloc(sizeof(float) * reps);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = MHD_OK;
+  if (!src || !times) rc = MHD_ERR_INVALID_ARG;
+  if (rc == MHD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = MHD_ERR_HIP;
+  for (int i = 0; i < n; ++i)
+    if (src) src[i] = ctxs[i]->cur;
+  const int def_tile = default_tile(ctxs[0]->p.precision);
+  float best = 1e30f, def_ms = -1.0f;
+  int best_tile = def_tile, best_cap = 0, tried = 0;
+  for (int ti = 0; ti < ntile && rc == MHD_OK; ++ti)
+    for (int ci = 0; ci < ncap && rc == MHD_OK; ++ci) {
+      const int cap = caps[ci];
+      // caps at or above every box's nz give the same shape as nz: time once
+      bool dup = false;
+      if (cap > 0) {
+        dup = true;
+        for (int i = 0; i < n; ++i)
+          if (ctxs[i]->p.nz > caps[ci - 1] || caps[ci - 1] == 0) dup = false;
+      }
+      if (dup) continue;
+      for (int i = 0; i < n && rc == MHD_OK; ++i) rc = apply_shape(ctxs[i], tiles[ti], cap);
+      if (rc != MHD_OK) break;
+      // the first launch warms up; the median of the timed ones counts
+      for (int r = 0; r <= reps && rc == MHD_OK; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess || launch_stage(ctxs, src, n, 0, st) != hipSuccess ||
+            hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = MHD_ERR_HIP;
+          break;
+        }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MHD_ERR_HIP;
+        if (r > 0) times[r - 1] = ms;
+      }
+      if (rc != MHD_OK) break;
+      for (int a = 1; a < reps; ++a)  // insertion sort of a few values
+        for (int b = a; b > 0 && times[b] < times[b - 1]; --b) {
+          float t = times[b];
+          times[b] = times[b - 1];
+          times[b - 1] = t;
+        }
+      const float med = times[reps / 2];
+      ++tried;
+      if (tiles[ti] == def_tile && cap == 0) def_ms = med;
+      if (med < best) {
+        best = med;
+        best_tile = tiles[ti];
+        best_cap = cap;
+      }
+    }
+  if (rc == MHD_OK)
+    for (int i = 0; i < n && rc == MHD_OK; ++i) rc = apply_shape(ctxs[i], best_tile, best_cap);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  free(src);
+  free(times);
+  if (rc == MHD_OK && out) {
+    out->tile = best_tile;
+    out->zchunk_cap = best_cap;
+    out->best_ms = best;
+    out->default_ms = def_ms;
+    out->candidates = tried;
+  }
+  return rc;
 }
 
 int mhd_destroy(mhd_ctx* c) {

@@ -106,3 +106,39 @@ def rel_err(a, b):
     if den == 0.0:
         return float(np.max(np.abs(a - b)))
     return float(np.max(np.abs(a - b))) / den
+
+
+# One RK2 cycle of the scheme reads, per stage, two cells on each side of a cell
+# (the van Leer slopes of both face states), so a periodic window of the state
+# reproduces the whole-box result of one cycle except within 4 cells of its
+# edges.  WINDOW_MARGIN leaves two more cells of slack.
+WINDOW_MARGIN = 6
+
+
+def window_index(center, size, dims):
+    """Periodic index vectors (x, y, z) of a size^3 window whose interior
+    starts at center - size // 2 on a box of dims = (nx, ny, nz)."""
+    return [np.arange(center[d] - size // 2, center[d] - size // 2 + size) % dims[d]
+            for d in range(3)]
+
+
+def take_window(s, idx):
+    """The window of every field of s (arrays [nz][ny][nx]) at idx = (ix, iy, iz)."""
+    return {f: np.ascontiguousarray(s[f][np.ix_(idx[2], idx[1], idx[0])]) for f in s}
+
+
+def inner(s, margin=WINDOW_MARGIN):
+    sl = (slice(margin, -margin),) * 3
+    return {f: s[f][sl] for f in s}
+
+
+def oracle_window_cycle(s, idx, dims, l, dt, riemann=O.HLLD, gamma=5.0 / 3.0):
+    """One oracle RK2 cycle with step dt on the periodic window idx of s;
+    returns the window's interior (valid part)."""
+    w = take_window(s, idx)
+    n = [len(i) for i in idx]
+    h = [l[d] / dims[d] for d in range(3)]
+    p = O.Params(n[0], n[1], n[2], n[0] * h[0], n[1] * h[1], n[2] * h[2], gamma=gamma,
+                 riemann=riemann)
+    O.step(p, w, 0.0, dt, 1)
+    return inner(w)

@@ -65,3 +65,16 @@ def test_workspace_bytes_and_argument_checks():
     assert L.mhd_step(None, 1, 0.0) == _lib.MHD_ERR_INVALID_ARG
     assert L.mhd_destroy(None) == _lib.MHD_OK
     assert _lib.status_string(_lib.MHD_ERR_NONPHYSICAL).startswith("non-physical")
+
+
+def test_launch_shape_and_tuner_argument_checks():
+    from paper_2304_13746_amd import _lib
+    L = _lib.lib()
+    t, z = C.c_int(), C.c_int()
+    assert L.mhd_set_launch(None, 0, 0) == _lib.MHD_ERR_INVALID_ARG
+    assert L.mhd_get_launch(None, C.byref(t), C.byref(z)) == _lib.MHD_ERR_INVALID_ARG
+    res = _lib.TuneResult()
+    assert L.mhd_tune(None, 1, 3, None, C.byref(res)) == _lib.MHD_ERR_INVALID_ARG
+    arr = (C.c_void_p * 1)(None)
+    assert L.mhd_tune(arr, 1, 3, None, C.byref(res)) == _lib.MHD_ERR_INVALID_ARG
+    assert L.mhd_tune(arr, 0, 3, None, C.byref(res)) == _lib.MHD_ERR_INVALID_ARG

@@ -1,0 +1,157 @@
+"""Parity at the full workload sizes, on sampled outputs and on properties that
+hold at any size.
+
+* 512^3 turbulence (k^-5/3 on 2 <= k <= 64, rms Mach 1, B = (0.1, 0.1, 0)):
+  one RK2 cycle on the GPU with the default launch shape; the first step equals
+  the oracle's eq. (cfl) step on the whole box; periodic windows around seeded
+  sample points (and one across the periodic corner) run through the oracle
+  reproduce the GPU result in the window interiors, bit for bit in FP64 and to
+  1e-5 in FP32 (the window property itself is pinned on the CPU in
+  test_oracle_scheme.py).  20 cycles conserve mass, momentum, energy and the
+  mean field to round-off and keep div B at round-off (compensated FP64 sums).
+* 64 uneven boxes (edges 16-128): one cycle of the autotuned, graph-captured
+  batch against the oracle on every box.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import FIELDS, bit_equal, max_rel, need_gpu
+from helpers import inner, oracle_window_cycle, take_window, window_index
+from paper_2304_13746_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+N5 = 512
+WIN = 28  # window edge; 16^3 interior after the margin
+
+
+@pytest.fixture(scope="module")
+def c5_state():
+    need_gpu()
+    print("generating the 512^3 input", flush=True)
+    s = I.turbulence(N5, seed=2304, spectrum="kolmogorov", kmin=2.0, kmax=64.0, mach=1.0,
+                     b0=(0.1, 0.1, 0.0))
+    s.pop("_l")
+    return s
+
+
+def sample_centers(n, count=3, seed=2304):
+    rng = np.random.default_rng(seed)
+    return [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(count)] + [(0, 0, 0)]
+
+
+def gpu_window(torch, g, idx):
+    """Window idx of the GPU fields g (torch tensors [nz][ny][nx]) as numpy."""
+    ix, iy, iz = (torch.as_tensor(i, device=g["rho"].device) for i in idx)
+    out = {}
+    for f in FIELDS:
+        a = g[f].index_select(0, iz).index_select(1, iy).index_select(2, ix)
+        out[f] = a.double().cpu().numpy()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c5_512_one_cycle_sampled(c5_state, precision):
+    torch = need_gpu()
+    from paper_2304_13746_amd.box import MHDBox
+    s = c5_state if precision == "fp64" else I.to_float32_exact(c5_state)
+    dims = (N5, N5, N5)
+    box = MHDBox(*dims, precision=precision)
+    box.set_state(s)
+    box.step(1)
+    g, t, _, rc = box.get_state()
+    assert rc == 0
+    p = O.Params(*dims)
+    dt = 0.3 / O.max_invdt(p, s)
+    print(f"512^3 {precision}: gpu dt {t!r} oracle dt {dt!r}", flush=True)
+    if precision == "fp64":
+        assert t == dt
+    else:
+        assert abs(t - dt) <= 1e-5 * dt
+    worst = 0.0
+    for c in sample_centers(N5):
+        idx = window_index(c, WIN, dims)
+        ref = oracle_window_cycle(s, idx, dims, (1.0, 1.0, 1.0), t)
+        got = inner(gpu_window(torch, g, idx))
+        err = max_rel(got, ref)
+        worst = max(worst, err)
+        if precision == "fp64":
+            assert bit_equal(got, ref), c
+        else:
+            assert err <= 1e-5, (c, err)
+    print(f"512^3 {precision}: worst window max rel {worst:.3e}")
+    box.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c5_512_conservation_20_cycles(c5_state, precision):
+    need_gpu()
+    from paper_2304_13746_amd.box import MHDBox
+    s = c5_state if precision == "fp64" else I.to_float32_exact(c5_state)
+    box = MHDBox(N5, N5, N5, precision=precision)
+    box.set_state(s)
+    d0 = box.diagnostics()
+    ref = O.diagnostics(O.Params(N5, N5, N5), s)
+    for k in ("mass", "energy"):
+        assert abs(d0[k] - ref[k]) <= 1e-12 * abs(ref[k])
+    box.step(20)
+    d1 = box.diagnostics()
+    assert d1["status"] == 0
+    g, t, _, _ = box.get_state()
+    scale_m = max(float(g[f].abs().double().mean()) for f in ("mx", "my", "mz"))
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    print(f"512^3 {precision} after 20 cycles (t={t:.4g}): mass {d1['mass'] - d0['mass']:.3e} "
+          f"energy {d1['energy'] - d0['energy']:.3e} mom {d1['mom'] - d0['mom']} "
+          f"bflux {d1['bflux'] - d0['bflux']} divb_max {d1['divb_max']:.3e}")
+    assert abs(d1["mass"] - d0["mass"]) <= tol * abs(d0["mass"])
+    assert abs(d1["energy"] - d0["energy"]) <= tol * abs(d0["energy"])
+    assert np.all(np.abs(d1["mom"] - d0["mom"]) <= tol * scale_m)
+    assert np.all(np.abs(d1["bflux"] - d0["bflux"]) <= tol * 0.1)
+    # |div B| dx / |B| stays at the rounding level of the field update
+    bmax = max(float(g[f].abs().max()) for f in ("bx", "by", "bz"))
+    assert d1["divb_max"] / N5 / bmax <= (1e-13 if precision == "fp64" else 1e-5)
+    box.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_c3_batch_full_size_vs_oracle(precision):
+    """The 64-box batch of the batched benchmark (tuned launch shape, captured
+    graph), one cycle, against the oracle on every box."""
+    torch = need_gpu()
+    from paper_2304_13746_amd.autotune import Tuner
+    from paper_2304_13746_amd.batch import BoxBatch
+    from paper_2304_13746_amd.box import MHDBox
+    spec = I.batch_boxes(64, seed=2304)
+    stream = torch.cuda.Stream()
+    boxes, inputs = [], []
+    for sp in spec:
+        st = sp["state"] if precision == "fp64" else I.to_float32_exact(sp["state"])
+        bx = MHDBox(*sp["dims"], *sp["l"], precision=precision, stream=stream)
+        bx.set_state(st)
+        boxes.append(bx)
+        inputs.append(st)
+    batch = BoxBatch(boxes)
+    with tempfile.TemporaryDirectory() as d:
+        choice = batch.tune(Tuner(os.path.join(d, "tune.json"), reps=2), force=True)
+    print("tuned", choice)
+    graph = batch.capture(1)
+    graph.replay()
+    worst = 0.0
+    for sp, st, bx in zip(spec, inputs, boxes):
+        g, t, _, rc = bx.get_state_numpy()
+        assert rc == 0
+        o = O.copy_state(st)
+        p = O.Params(*sp["dims"], *sp["l"])
+        to, _, _ = O.step(p, o, 0.0, 0.0, 1)
+        if precision == "fp64":
+            assert bit_equal(g, o) and t == to, sp["dims"]
+        else:
+            err = max_rel(g, o)
+            worst = max(worst, err)
+            assert err <= 1e-5, (sp["dims"], err)
+            assert abs(t - to) <= 1e-5 * to
+    print(f"64 boxes {precision}: worst max rel {worst:.3e}")

@@ -263,3 +263,31 @@ def test_cyclic_axis_permutation_3d(solver):
     a = permute_xyz(outs[0])
     for f in O.FIELDS:
         assert np.max(np.abs(a[f] - outs[1][f])) <= 1e-12 * max(1.0, np.max(np.abs(a[f]))), f
+
+
+def test_one_cycle_is_local_so_windows_reproduce_the_box():
+    """Locality used by the full-size sampled parity tests: one oracle cycle on
+    a periodic window equals the whole-box cycle away from the window edges
+    (bit for bit beyond the margin), and differs near them (the margin is not
+    vacuous)."""
+    from helpers import WINDOW_MARGIN, inner, oracle_window_cycle, take_window, window_index
+    n = 40
+    s = I.turbulence(n, seed=5, kpeak=3.0, mach=1.2, b0=(0.3, -0.2, 0.1))
+    l = s.pop("_l")
+    p = O.Params(n, n, n, *l)
+    dt = 0.3 / O.max_invdt(p, s)
+    full = O.copy_state(s)
+    O.step(p, full, 0.0, dt, 1)
+    for c in ((20, 23, 26), (0, 0, 0), (39, 5, 17)):
+        idx = window_index(c, 28, (n, n, n))
+        got = oracle_window_cycle(s, idx, (n, n, n), l, dt)
+        ref = inner(take_window(full, idx))
+        for f in O.FIELDS:
+            assert np.array_equal(got[f], ref[f]), (c, f)
+        # with no margin at all the window edges are wrong
+        w = take_window(s, idx)
+        pw = O.Params(28, 28, 28, 28 * l[0] / n, 28 * l[1] / n, 28 * l[2] / n)
+        O.step(pw, w, 0.0, dt, 1)
+        whole = take_window(full, idx)
+        assert not all(np.array_equal(w[f], whole[f]) for f in O.FIELDS)
+    assert WINDOW_MARGIN >= 4
