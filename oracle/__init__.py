@@ -25,7 +25,8 @@ LIB = os.path.join(HERE, "libmhd_oracle.so")
 FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
 
 HLLD, HLL = 0, 1
-RK2, EULER = 0, 1
+RK2, EULER, RK3 = 0, 1, 2
+EMF_EC, EMF_E0, EMF_ARITH = 0, 1, 2
 OK, ERR_INVALID_ARG, ERR_NOMEM, ERR_NONPHYSICAL = 0, -1, -2, -4
 
 # -ffp-contract=off: no fused multiply-add, every expression rounds as written.
@@ -46,7 +47,7 @@ class _Params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
                 ("gamma", C.c_double), ("cfl", C.c_double),
-                ("riemann", C.c_int), ("integrator", C.c_int)]
+                ("riemann", C.c_int), ("integrator", C.c_int), ("emf", C.c_int)]
 
 
 class _State(C.Structure):
@@ -69,6 +70,7 @@ def lib():
         L.orc_max_invdt.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp]
         L.orc_step.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, C.c_int, C.c_double]
         L.orc_diagnostics.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp]
+        L.orc_mass_flux.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, dp]
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
         L.orc_vanleer.restype = C.c_double
         for fn in (L.orc_fast_speed, L.orc_slow_speed):
@@ -78,6 +80,8 @@ def lib():
         L.orc_phys_flux.argtypes = [C.c_double, dp, C.c_double, dp, dp]
         L.orc_corner_emf.argtypes = [C.c_double] * 12
         L.orc_corner_emf.restype = C.c_double
+        L.orc_corner_emf_scheme.argtypes = [C.c_int] + [C.c_double] * 12
+        L.orc_corner_emf_scheme.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -95,10 +99,11 @@ class Params:
     cfl: float = 0.3
     riemann: int = HLLD
     integrator: int = RK2
+    emf: int = EMF_EC
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.gamma,
-                       self.cfl, self.riemann, self.integrator)
+                       self.cfl, self.riemann, self.integrator, self.emf)
 
 
 def _dptr(a: np.ndarray):
@@ -124,6 +129,16 @@ def max_invdt(p: Params, s: dict) -> float:
     if rc not in (OK,):
         raise RuntimeError(f"orc_max_invdt failed: {rc}")
     return out.value
+
+
+def mass_flux(p: Params, s: dict):
+    """Riemann mass flux on every (x, y, z) face of the state, three [nz][ny][nx]
+    arrays (index c = face at the lower side of cell c)."""
+    out = [np.zeros((p.nz, p.ny, p.nx)) for _ in range(3)]
+    rc = lib().orc_mass_flux(C.byref(p.c()), C.byref(_cstate(p, s)), *[_dptr(a) for a in out])
+    if rc != OK:
+        raise RuntimeError(f"orc_mass_flux failed: {rc}")
+    return out
 
 
 def step(p: Params, s: dict, t: float, dt_next: float, nsteps: int, t_stop: float = 0.0,
@@ -182,6 +197,11 @@ def phys_flux(gamma: float, w, bn: float):
 
 def corner_emf(a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3) -> float:
     return lib().orc_corner_emf(a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3)
+
+
+def corner_emf_scheme(scheme, a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3) -> float:
+    return lib().orc_corner_emf_scheme(scheme, a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3,
+                                       sp1, sp3)
 
 
 def num_threads() -> int:

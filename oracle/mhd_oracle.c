@@ -18,7 +18,7 @@
  *       solve yields c_max for the CFL condition (eq. cfl).
  *   S5  conservative update of (rho, m, E) by the flux divergence (eq. gal).
  *   S7  corner EMFs with the upwind-by-contact scheme E^c of Gardiner & Stone
- *       (2005), the default of Sec. 2.4.
+ *       (2005), the default of Sec. 2.4, or its E^0 and arithmetic variants.
  *   S8  face-B update by the discrete Stokes theorem (constrained transport,
  *       eq. ind_short).
  *   Stages are combined as U_s = w_s U* + w0_s U_0 (Sec. 2.7, Tab. weights);
@@ -47,6 +47,7 @@ typedef struct {
   double idl[3]; /* 1 / dl_d */
   double dv;     /* cell volume */
   int riemann;
+  int emf;
 } grid_t;
 
 static void grid_init(grid_t* g, const orc_params* p) {
@@ -63,6 +64,7 @@ static void grid_init(grid_t* g, const orc_params* p) {
   g->idl[2] = 1.0 / dz;
   g->dv = (dx * dy) * dz;
   g->riemann = p->riemann;
+  g->emf = p->emf;
 }
 
 static int check_params(const orc_params* p) {
@@ -70,7 +72,10 @@ static int check_params(const orc_params* p) {
   if (!(p->lx > 0) || !(p->ly > 0) || !(p->lz > 0)) return ORC_ERR_INVALID_ARG;
   if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl < 1.0)) return ORC_ERR_INVALID_ARG;
   if (p->riemann != ORC_HLLD && p->riemann != ORC_HLL) return ORC_ERR_INVALID_ARG;
-  if (p->integrator != ORC_RK2 && p->integrator != ORC_EULER) return ORC_ERR_INVALID_ARG;
+  if (p->integrator != ORC_RK2 && p->integrator != ORC_EULER && p->integrator != ORC_RK3)
+    return ORC_ERR_INVALID_ARG;
+  if (p->emf != ORC_EMF_EC && p->emf != ORC_EMF_E0 && p->emf != ORC_EMF_ARITH)
+    return ORC_ERR_INVALID_ARG;
   return ORC_OK;
 }
 
@@ -334,6 +339,19 @@ double orc_corner_emf(double a1, double a2, double b1, double b2, double c00, do
   return 0.25 * ((((a1 + a2) + (b1 + b2)) + (dq3 - dq1)) + (dp3 - dp1));
 }
 
+/* The corner-EMF schemes of Sec. 2.4 built on the Riemann face EMFs (Gardiner &
+ * Stone 2005): E^c upwinds the derivative terms by the mass-flux sign; E^0 takes
+ * the plain mean of the two candidate derivatives on every side (the E^c
+ * formula with every upwind switch at its tie value); the arithmetic scheme is
+ * the mean of the four face EMFs alone. */
+double orc_corner_emf_scheme(int scheme, double a1, double a2, double b1, double b2, double c00,
+                             double c10, double c01, double c11, double sq1, double sq3,
+                             double sp1, double sp3) {
+  if (scheme == ORC_EMF_ARITH) return 0.25 * ((a1 + a2) + (b1 + b2));
+  if (scheme == ORC_EMF_E0) return orc_corner_emf(a1, a2, b1, b2, c00, c10, c01, c11, 0, 0, 0, 0);
+  return orc_corner_emf(a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3);
+}
+
 /* --------------------------------------------------------------- stage */
 
 enum { W_RHO, W_VX, W_VY, W_VZ, W_BX, W_BY, W_BZ, W_P, NW };
@@ -479,23 +497,26 @@ static void emfs(const grid_t* g, work_t* w) {
         /* E_z at (i-1/2, j-1/2, k): P = x, Q = y */
         {
           long cjm = at(g, i, jm, k), cim = at(g, im, j, k), cimjm = at(g, im, jm, k);
-          w->ed[2][c] = orc_corner_emf(-fx[F_B1][c], -fx[F_B1][cjm], fy[F_B2][c], fy[F_B2][cim],
-                                       w->er[2][cimjm], w->er[2][cjm], w->er[2][cim], w->er[2][c],
-                                       fx[F_RHO][c], fx[F_RHO][cjm], fy[F_RHO][c], fy[F_RHO][cim]);
+          w->ed[2][c] = orc_corner_emf_scheme(
+              g->emf, -fx[F_B1][c], -fx[F_B1][cjm], fy[F_B2][c], fy[F_B2][cim], w->er[2][cimjm],
+              w->er[2][cjm], w->er[2][cim], w->er[2][c], fx[F_RHO][c], fx[F_RHO][cjm],
+              fy[F_RHO][c], fy[F_RHO][cim]);
         }
         /* E_x at (i, j-1/2, k-1/2): P = y, Q = z */
         {
           long ckm = at(g, i, j, km), cjm = at(g, i, jm, k), cjmkm = at(g, i, jm, km);
-          w->ed[0][c] = orc_corner_emf(-fy[F_B1][c], -fy[F_B1][ckm], fz[F_B2][c], fz[F_B2][cjm],
-                                       w->er[0][cjmkm], w->er[0][ckm], w->er[0][cjm], w->er[0][c],
-                                       fy[F_RHO][c], fy[F_RHO][ckm], fz[F_RHO][c], fz[F_RHO][cjm]);
+          w->ed[0][c] = orc_corner_emf_scheme(
+              g->emf, -fy[F_B1][c], -fy[F_B1][ckm], fz[F_B2][c], fz[F_B2][cjm], w->er[0][cjmkm],
+              w->er[0][ckm], w->er[0][cjm], w->er[0][c], fy[F_RHO][c], fy[F_RHO][ckm],
+              fz[F_RHO][c], fz[F_RHO][cjm]);
         }
         /* E_y at (i-1/2, j, k-1/2): P = z, Q = x */
         {
           long cim = at(g, im, j, k), ckm = at(g, i, j, km), cimkm = at(g, im, j, km);
-          w->ed[1][c] = orc_corner_emf(-fz[F_B1][c], -fz[F_B1][cim], fx[F_B2][c], fx[F_B2][ckm],
-                                       w->er[1][cimkm], w->er[1][cim], w->er[1][ckm], w->er[1][c],
-                                       fz[F_RHO][c], fz[F_RHO][cim], fx[F_RHO][c], fx[F_RHO][ckm]);
+          w->ed[1][c] = orc_corner_emf_scheme(
+              g->emf, -fz[F_B1][c], -fz[F_B1][cim], fx[F_B2][c], fx[F_B2][ckm], w->er[1][cimkm],
+              w->er[1][cim], w->er[1][ckm], w->er[1][c], fz[F_RHO][c], fz[F_RHO][cim],
+              fx[F_RHO][c], fx[F_RHO][ckm]);
         }
       }
     }
@@ -503,11 +524,11 @@ static void emfs(const grid_t* g, work_t* w) {
 }
 
 /* One application of the stage operator S_dt (steps S1-S8) to src, written to
- * dst; if base is given, dst = 0.5 S_dt(src) + 0.5 base (second RK2 stage; base
- * and dst may be the same arrays).  If maxinv is given it receives the CFL
- * maximum of eq. (cfl) measured on src. */
-static int stage(const grid_t* g, const orc_state* src, const orc_state* base, orc_state* dst,
-                 double dt, double* maxinv, work_t* w) {
+ * dst; if base is given, dst = ws S_dt(src) + w0 base (later stages of a
+ * Runge-Kutta cycle, Sec. 2.7; base and dst may be the same arrays).  If maxinv
+ * is given it receives the CFL maximum of eq. (cfl) measured on src. */
+static int stage(const grid_t* g, const orc_state* src, const orc_state* base, double ws,
+                 double w0, orc_state* dst, double dt, double* maxinv, work_t* w) {
   int bad = prim_all(g, src, w);
   for (int d = 0; d < 3; ++d) faces(g, src, w, d);
   emfs(g, w);
@@ -539,7 +560,7 @@ static int stage(const grid_t* g, const orc_state* src, const orc_state* base, o
         for (int q = 0; q < 5; ++q) {
           double v = ((us[q][c] - tx * (fx[q][cxp] - fx[q][c])) - ty * (fy[q][cyp] - fy[q][c])) -
                      tz * (fz[q][czp] - fz[q][c]);
-          ud[q][c] = base ? 0.5 * v + 0.5 * ub[q][c] : v;
+          ud[q][c] = base ? ws * v + w0 * ub[q][c] : v;
         }
         /* S8: discrete Stokes on each face */
         const double* ex = w->ed[0];
@@ -549,9 +570,9 @@ static int stage(const grid_t* g, const orc_state* src, const orc_state* base, o
         double byn = (src->by[c] - tz * (ex[czp] - ex[c])) + tx * (ez[cxp] - ez[c]);
         double bzn = (src->bz[c] - tx * (ey[cxp] - ey[c])) + ty * (ex[cyp] - ex[c]);
         if (base) {
-          bxn = 0.5 * bxn + 0.5 * base->bx[c];
-          byn = 0.5 * byn + 0.5 * base->by[c];
-          bzn = 0.5 * bzn + 0.5 * base->bz[c];
+          bxn = ws * bxn + w0 * base->bx[c];
+          byn = ws * byn + w0 * base->by[c];
+          bzn = ws * bzn + w0 * base->bz[c];
         }
         dst->bx[c] = bxn;
         dst->by[c] = byn;
@@ -617,6 +638,26 @@ int orc_max_invdt(const orc_params* p, const orc_state* s, double* out) {
   return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
 }
 
+/* S3 mass fluxes F_rho on every x, y and z face of the state (the quantity whose
+ * sign drives the upwind choice of the E^c corner EMF, Sec. 2.4). */
+int orc_mass_flux(const orc_params* p, const orc_state* s, double* fx, double* fy, double* fz) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!s || !fx || !fy || !fz) return ORC_ERR_INVALID_ARG;
+  grid_t g;
+  grid_init(&g, p);
+  work_t w;
+  if (work_alloc(&w, g.n)) return ORC_ERR_NOMEM;
+  int bad = prim_all(&g, s, &w);
+  double* out[3] = {fx, fy, fz};
+  for (int d = 0; d < 3; ++d) {
+    faces(&g, s, &w, d);
+    memcpy(out[d], w.f[d][F_RHO], sizeof(double) * g.n);
+  }
+  free(w.block);
+  return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
 /* step to take this cycle: the CFL step, clipped so as not to pass t_stop */
 static double clip_dt(double dt, double t, double t_stop) {
   if (t_stop > 0.0) {
@@ -641,11 +682,16 @@ int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int 
     *dt_next = p->cfl / mi;
   }
   work_t w;
-  orc_state tmp;
-  double* tblock;
+  orc_state tmp, tmp2;
+  double *tblock, *tblock2 = NULL;
   if (work_alloc(&w, g.n)) return ORC_ERR_NOMEM;
   if (state_alloc(&tmp, g.n, &tblock)) {
     free(w.block);
+    return ORC_ERR_NOMEM;
+  }
+  if (p->integrator == ORC_RK3 && state_alloc(&tmp2, g.n, &tblock2)) {
+    free(w.block);
+    free(tblock);
     return ORC_ERR_NOMEM;
   }
   int bad = 0;
@@ -653,10 +699,15 @@ int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int 
     double dt = clip_dt(*dt_next, *t, t_stop);
     double mi = 0.0;
     /* stage 1: U_1 = S_dt(U_0)  (w_1 = 1, w0_1 = 0) */
-    bad |= stage(&g, s, NULL, &tmp, dt, &mi, &w);
+    bad |= stage(&g, s, NULL, 1.0, 0.0, &tmp, dt, &mi, &w);
     if (p->integrator == ORC_RK2) {
       /* stage 2: U^{n+1} = 1/2 S_dt(U_1) + 1/2 U_0 */
-      bad |= stage(&g, &tmp, s, s, dt, NULL, &w);
+      bad |= stage(&g, &tmp, s, 0.5, 0.5, s, dt, NULL, &w);
+    } else if (p->integrator == ORC_RK3) {
+      /* stage 2: U_2 = 1/4 S_dt(U_1) + 3/4 U_0; stage 3: U^{n+1} = 2/3 S_dt(U_2)
+       * + 1/3 U_0 */
+      bad |= stage(&g, &tmp, s, 0.25, 0.75, &tmp2, dt, NULL, &w);
+      bad |= stage(&g, &tmp2, s, 2.0 / 3.0, 1.0 / 3.0, s, dt, NULL, &w);
     } else {
       memcpy(s->rho, tmp.rho, sizeof(double) * g.n);
       memcpy(s->mx, tmp.mx, sizeof(double) * g.n);
@@ -672,6 +723,7 @@ int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int 
   }
   free(w.block);
   free(tblock);
+  free(tblock2);
   return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
 }
 

@@ -20,7 +20,9 @@ extern "C" {
 #endif
 
 enum { ORC_HLLD = 0, ORC_HLL = 1 };
-enum { ORC_RK2 = 0, ORC_EULER = 1 };
+enum { ORC_RK2 = 0, ORC_EULER = 1, ORC_RK3 = 2 };
+/* corner-EMF schemes of Sec. 2.4: E^c (default), E^0, arithmetic average */
+enum { ORC_EMF_EC = 0, ORC_EMF_E0 = 1, ORC_EMF_ARITH = 2 };
 
 enum {
   ORC_OK = 0,
@@ -35,7 +37,8 @@ typedef struct {
   double gamma;        /* adiabatic index, > 1 */
   double cfl;          /* sigma_CFL of eq. (cfl), in (0, 1) */
   int riemann;         /* ORC_HLLD or ORC_HLL */
-  int integrator;      /* ORC_RK2 or ORC_EULER (Tab. weights) */
+  int integrator;      /* ORC_RK2, ORC_EULER or ORC_RK3 (Tab. weights) */
+  int emf;             /* ORC_EMF_EC, ORC_EMF_E0 or ORC_EMF_ARITH */
 } orc_params;
 
 typedef struct {
@@ -45,6 +48,10 @@ typedef struct {
 
 /* Max over the volume of sum_d c_max,d / dl_d (eq. cfl) for the given state. */
 int orc_max_invdt(const orc_params* p, const orc_state* s, double* out);
+
+/* Mass flux F_rho of the Riemann solve (S3) on every face of the state: fx[c] on
+ * the x-face at (i-1/2, j, k) of cell c, fy and fz likewise (arrays of n cells). */
+int orc_mass_flux(const orc_params* p, const orc_state* s, double* fx, double* fy, double* fz);
 
 /* Advance nsteps cycles in place.  *dt_next is the step to use for the first
  * cycle (pass <= 0 to compute it from the state); on return it holds the CFL
@@ -85,6 +92,10 @@ void orc_phys_flux(double gamma, const double w[7], double bn, double u[7], doub
 double orc_corner_emf(double a1, double a2, double b1, double b2,
                       double c00, double c10, double c01, double c11,
                       double sq1, double sq3, double sp1, double sp3);
+/* The same corner EMF for any of the ORC_EMF_* schemes. */
+double orc_corner_emf_scheme(int scheme, double a1, double a2, double b1, double b2,
+                             double c00, double c10, double c01, double c11,
+                             double sq1, double sq3, double sp1, double sp3);
 
 #ifdef __cplusplus
 }

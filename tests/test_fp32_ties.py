@@ -1,0 +1,49 @@
+"""Host-side pieces of the FP32 comparisons: the oracle's face mass fluxes and
+the E^c upwind-tie mask built from them."""
+import numpy as np
+
+import oracle as O
+from gpu_util import TIE_DILATE, upwind_tie_cells
+from paper_2304_13746_amd import inputs as I
+
+
+def uniform(n, vx, vy=0.0, vz=0.0, rho=1.0, p=0.6, b=(0.3, 0.2, 0.1)):
+    sh = (n, n, n)
+    return I.assemble(rho, np.full(sh, vx), np.full(sh, vy), np.full(sh, vz), p,
+                      np.full(sh, b[0]), np.full(sh, b[1]), np.full(sh, b[2]), 5.0 / 3.0)
+
+
+def test_mass_flux_of_uniform_flow_is_rho_v():
+    """A uniform state's Riemann mass flux is the physical one, rho v_n."""
+    n = 8
+    s = uniform(n, 0.3, -0.2, 0.7, rho=1.3)
+    fx, fy, fz = O.mass_flux(O.Params(n, n, n), s)
+    for a, v in ((fx, 0.3), (fy, -0.2), (fz, 0.7)):
+        assert np.allclose(a, 1.3 * v, rtol=1e-14, atol=0)
+
+
+def test_tie_mask_marks_only_near_zero_mass_flux():
+    n = 16
+    # turbulence: no face flux within 1e-5 of the largest one, nothing marked
+    s = I.turbulence(n, seed=3, kpeak=2.0, mach=0.8, b0=(0.2, 0.0, 0.1))
+    l = s.pop("_l")
+    p = O.Params(n, n, n, *l)
+    near = upwind_tie_cells(p, s, 0.3 / O.max_invdt(p, s))
+    assert near.mean() < 0.01
+    # v_x crossing zero just off the x-faces 5 and 21 (1e-8 offset): those two
+    # slabs of faces carry a mass flux within rounding of zero and are marked
+    # (dilated); the first stage's y- and z-fluxes are exactly zero (v_y = v_z =
+    # 0, no ambiguity), so in stage 1 nothing else is marked
+    n = 32
+    x = (np.arange(n) + 0.5) / n
+    vx = np.broadcast_to(0.5 * np.sin(2 * np.pi * (x - 5.0 / n)) + 1e-8, (n, n, n)).copy()
+    sh = (n, n, n)
+    s = I.assemble(1.0, vx, np.zeros(sh), np.zeros(sh), 0.6, np.full(sh, 0.3),
+                   np.full(sh, 0.2), np.full(sh, 0.1), 5.0 / 3.0)
+    fx, _, _ = O.mass_flux(O.Params(n, n, n), s)
+    assert abs(fx[0, 0, 5]) < 1e-6 and abs(fx[0, 0, 21]) < 1e-6
+    near = upwind_tie_cells(O.Params(n, n, n), s, 1e-3, integrator="euler")
+    marked = set(np.unique(np.nonzero(near)[2]).tolist())
+    want = set(range(5 - TIE_DILATE - 1, 5 + TIE_DILATE + 1)) | \
+        set(range(21 - TIE_DILATE - 1, 21 + TIE_DILATE + 1))
+    assert {5, 21} <= marked <= want

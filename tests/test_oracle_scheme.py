@@ -291,3 +291,47 @@ def test_one_cycle_is_local_so_windows_reproduce_the_box():
         whole = take_window(full, idx)
         assert not all(np.array_equal(w[f], whole[f]) for f in O.FIELDS)
     assert WINDOW_MARGIN >= 4
+
+
+@pytest.mark.parametrize("name,integ", [("rk2", O.RK2), ("rk3", O.RK3)])
+def test_runge_kutta_cycle_is_tab_weights_composition(name, integ):
+    """Sec. 2.7: a cycle is U_s = w_s S_dt(U_{s-1}) + w0_s U_0 with the weights of
+    Tab. weights (golden values).  The oracle's multi-stage cycle equals that
+    composition of single Euler stages (S_dt alone), bit for bit."""
+    w = golden()["rk_weights"][name]
+    n = 12
+    s0 = I.turbulence(n, seed=21, kpeak=2.0, mach=0.9, b0=(0.2, 0.1, -0.3))
+    l = s0.pop("_l")
+    dt = 0.3 / O.max_invdt(O.Params(n, n, n, *l), s0)
+    pe = O.Params(n, n, n, *l, integrator=O.EULER)
+    prev = O.copy_state(s0)
+    for ws, w0 in zip(w["w"], w["w0"]):
+        star = O.copy_state(prev)
+        O.step(pe, star, 0.0, dt, 1)
+        prev = {f: ws * star[f] + w0 * s0[f] for f in O.FIELDS}
+    got = O.copy_state(s0)
+    O.step(O.Params(n, n, n, *l, integrator=integ), got, 0.0, dt, 1)
+    for f in O.FIELDS:
+        assert np.array_equal(got[f], prev[f]), f
+
+
+def test_rk3_temporal_error_below_rk2():
+    """On a smooth linear wave the time-stepping error (against a run with a
+    16x smaller CFL number) of the third-order cycle is far below that of the
+    second-order one at the same CFL number, and shrinks with dt."""
+    from helpers import cons8
+
+    def run(integ, cfl, t_end=0.2):
+        s, info = I.linear_wave("fast", 8)
+        p = O.Params(*info["dims"], *info["l"], cfl=cfl, integrator=integ)
+        t, dt = 0.0, 0.0
+        while t < t_end:
+            t, dt, _ = O.step(p, s, t, dt, 1, t_end)
+        return cons8(s)
+
+    ref = run(O.RK3, 0.025)
+    err = lambda a: max(float(np.max(np.abs(x - y))) for x, y in zip(a, ref))
+    e2, e3 = err(run(O.RK2, 0.4)), err(run(O.RK3, 0.4))
+    e3h = err(run(O.RK3, 0.2))
+    assert e3 < e2 / 8
+    assert e3h < e3 / 1.5
