@@ -64,12 +64,14 @@ def counter_traffic(precision: str):
     return float(m.group(1)) if m else None
 
 
-def run_gpu(state, precision: str, steps: int, warmup: int, tile: int = 0, zchunk: int = 0):
+def run_gpu(state, precision: str, steps: int, warmup: int, tile: int = 0, zchunk: int = 0,
+            integrator: str = "rk2", emf: str = "ec", recon: str = "plm"):
     import torch
 
     from paper_2304_13746_amd.box import MHDBox
 
-    box = MHDBox(N, N, N, precision=precision, riemann="hlld", tile=tile, zchunk=zchunk)
+    box = MHDBox(N, N, N, precision=precision, riemann="hlld", tile=tile, zchunk=zchunk,
+                 integrator=integrator, emf=emf, recon=recon)
     box.set_state(state)
     box.step(warmup)
     torch.cuda.synchronize()
@@ -225,6 +227,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-box batched run")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the runs of the widened scheme options (RK3, LimO3, E^0, "
+                         "arithmetic EMF)")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests in the served replay (0: skip; the full stream is 5000)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
@@ -291,6 +296,24 @@ def main():
         f = results["fp32"]
         line["fp32"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "dtype": "f32",
                         "roofline": f["roofline"]}
+    if not args.no_next:
+        # widened scheme options on the same input: the third-order Runge-Kutta
+        # cycle (three stage launches per cycle), LimO3 reconstruction with RK3,
+        # and the E^0 / arithmetic corner EMFs (two launches per cycle)
+        nxt = {}
+        k = min(args.steps, 20)
+        for name, integ, emf, recon, nst in (("rk3", "rk3", "ec", "plm", 3),
+                                             ("limo3_rk3", "rk3", "ec", "limo3", 3),
+                                             ("emf_e0", "rk2", "e0", "plm", 2),
+                                             ("emf_arith", "rk2", "arith", "plm", 2)):
+            for prec in precs:
+                r = run_gpu(state, prec, k, 1, args.tile, args.zchunk, integ, emf, recon)
+                ms_step = r["ms_total"] / k
+                nxt[f"{name}_{prec}"] = {"value": N ** 3 / (ms_step * 1e-3), "unit": "cell-updates/s",
+                                         "ms_per_step": ms_step, "stage_launch_ms": ms_step / nst,
+                                         "rc": r["rc"]}
+                print(f"# {name} {prec}: {ms_step:.3f} ms/cycle", file=sys.stderr, flush=True)
+        line["next_rows"] = nxt
     if not args.no_batch:
         line["batched"] = batched_c3()
         print(f"# batched: {line['batched']['value']:.4e} cell-updates/s, "

@@ -6,9 +6,11 @@
  * energy with viscosity, gravity, resistivity and conduction set to zero) with the
  * Godunov finite-volume cycle of Sec. 2.2-2.7:
  *   conserved U = (rho, rho v, E) at cell centres and B on cell faces (Sec. 2.2,
- *   2.4); per stage: primitive reconstruction with the van Leer limiter (Sec. 2.3),
+ *   2.4); per stage: primitive reconstruction with the van Leer limiter or LimO3
+ *   (Sec. 2.3),
  *   an HLLD or HLL Riemann solve on every x, y and z face (Sec. 2.3), corner EMFs
- *   by the upwind-by-contact E^c scheme (Sec. 2.4), the flux-divergence update of U
+ *   by the upwind-by-contact E^c scheme or its E^0 and arithmetic variants
+ *   (Sec. 2.4), the flux-divergence update of U
  *   and the constrained-transport update of face B (eq. ind_short); stages combined
  *   as U_s = w_s U* + w0_s U_0 (Sec. 2.7, Tab. weights); time step from eq. (cfl).
  * Energy is E = p/(gamma-1) + rho v^2/2 + B^2/2, dimensionless units without 4 pi.
@@ -51,8 +53,13 @@ extern "C" {
 
 typedef enum { MHD_FP64 = 0, MHD_FP32 = 1 } mhd_precision;
 typedef enum { MHD_HLLD = 0, MHD_HLL = 1 } mhd_riemann;       /* Sec. 2.3 */
-typedef enum { MHD_EMF_EC = 0 } mhd_emf;                      /* E^c, Sec. 2.4 default */
-typedef enum { MHD_RK2 = 0, MHD_EULER = 1 } mhd_integrator;   /* Tab. weights */
+/* Corner-EMF schemes of Sec. 2.4 (Gardiner & Stone 2005): E^c (default), E^0
+ * and the arithmetic mean of the four face EMFs. */
+typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2 } mhd_emf;
+/* Reconstructions of Sec. 2.3: van Leer PLM (default) and the compact
+ * third-order LimO3 limiter (Cada & Torrilhon 2009), both on the primitives. */
+typedef enum { MHD_PLM = 0, MHD_LIMO3 = 1 } mhd_recon;
+typedef enum { MHD_RK2 = 0, MHD_EULER = 1, MHD_RK3 = 2 } mhd_integrator; /* Tab. weights */
 
 typedef struct mhd_ctx mhd_ctx; /* opaque */
 
@@ -74,6 +81,7 @@ typedef struct {
   void* stream;           /* hipStream_t to enqueue on (NULL: default stream) */
   int tile;               /* MHD_TILE_*, 0 = default (24x8) */
   int zchunk;             /* z-planes per thread block, 0 = automatic */
+  int recon;              /* mhd_recon */
 } mhd_params;
 
 typedef struct {
@@ -92,7 +100,9 @@ typedef struct {
 } mhd_diag;
 
 /* Device bytes a context with these parameters needs (only the grid, precision
- * and tile fields are read).  Returns 0 if the grid is invalid. */
+ * and integrator fields are read): two state buffers of 8 fields, three for
+ * MHD_RK3, plus under 1 MB of scalars and partial sums.  Returns 0 if the grid
+ * is invalid. */
 size_t mhd_workspace_bytes(const mhd_params* params);
 
 /* Validate params and build a context on the borrowed workspace.  *out receives
@@ -126,7 +136,7 @@ int mhd_get_diagnostics(mhd_ctx* ctx, mhd_diag* out);
  * launch), followed by one cycle-control launch for all of them; each box keeps
  * its own step size, time and status latch, and gives the same bits as
  * mhd_step on it alone.  All contexts must share device, precision, solver,
- * integrator and tile shape (else MHD_ERR_UNSUPPORTED); a null entry or a
+ * integrator, EMF scheme, reconstruction and tile shape (else MHD_ERR_UNSUPPORTED); a null entry or a
  * negative count is MHD_ERR_INVALID_ARG.  The contexts' own streams are not
  * synchronised with: order them against the batch stream first.  Asynchronous,
  * allocation-free, capture-safe. */

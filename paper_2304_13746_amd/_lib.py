@@ -21,8 +21,9 @@ MHD_ERR_UNSUPPORTED = -5
 
 MHD_FP64, MHD_FP32 = 0, 1
 MHD_HLLD, MHD_HLL = 0, 1
-MHD_EMF_EC = 0
-MHD_RK2, MHD_EULER = 0, 1
+MHD_EMF_EC, MHD_EMF_E0, MHD_EMF_ARITH = 0, 1, 2
+MHD_PLM, MHD_LIMO3 = 0, 1
+MHD_RK2, MHD_EULER, MHD_RK3 = 0, 1, 2
 TILE_16x16, TILE_24x8 = 1, 2
 
 EXPORTED = ("mhd_workspace_bytes", "mhd_create", "mhd_set_state", "mhd_step", "mhd_get_state",
@@ -37,7 +38,8 @@ class Params(C.Structure):
                 ("precision", C.c_int), ("riemann", C.c_int), ("emf", C.c_int),
                 ("integrator", C.c_int),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("stream", C.c_void_p), ("tile", C.c_int), ("zchunk", C.c_int)]
+                ("stream", C.c_void_p), ("tile", C.c_int), ("zchunk", C.c_int),
+                ("recon", C.c_int)]
 
 
 class StateView(C.Structure):

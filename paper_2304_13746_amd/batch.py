@@ -53,12 +53,12 @@ class BoxBatch:
 
     def capture(self, nsteps) -> "StepGraph":
         """Record the launches of ``step(nsteps)`` into a HIP graph on the batch's
-        stream (RK2 only: the buffer roles of an Euler cycle alternate on the
+        stream (RK2 or RK3: the buffer roles of an Euler cycle alternate on the
         host).  Each replay advances every box by its step count again, with
         dt and t kept on the device."""
         for b in self.boxes:
-            if b.params.integrator != L.MHD_RK2:
-                raise ValueError("graph capture needs the RK2 integrator")
+            if b.params.integrator == L.MHD_EULER:
+                raise ValueError("graph capture needs a Runge-Kutta integrator")
         g = torch.cuda.CUDAGraph()
         torch.cuda.synchronize()
         with torch.cuda.graph(g, stream=self.stream):

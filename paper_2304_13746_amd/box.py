@@ -18,7 +18,9 @@ from . import _lib as L
 FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
 PRECISION = {"fp64": L.MHD_FP64, "fp32": L.MHD_FP32}
 RIEMANN = {"hlld": L.MHD_HLLD, "hll": L.MHD_HLL}
-INTEGRATOR = {"rk2": L.MHD_RK2, "euler": L.MHD_EULER}
+INTEGRATOR = {"rk2": L.MHD_RK2, "euler": L.MHD_EULER, "rk3": L.MHD_RK3}
+EMF = {"ec": L.MHD_EMF_EC, "e0": L.MHD_EMF_E0, "arith": L.MHD_EMF_ARITH}
+RECON = {"plm": L.MHD_PLM, "limo3": L.MHD_LIMO3}
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
 
 
@@ -27,21 +29,23 @@ def _view(tensors: dict) -> L.StateView:
 
 
 def make_params(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, gamma=5.0 / 3.0, cfl=0.3, precision="fp64",
-                riemann="hlld", integrator="rk2", tile=0, zchunk=0) -> L.Params:
+                riemann="hlld", integrator="rk2", tile=0, zchunk=0, emf="ec",
+                recon="plm") -> L.Params:
     p = L.Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.lx, p.ly, p.lz = float(lx), float(ly), float(lz)
     p.gamma, p.cfl = float(gamma), float(cfl)
     p.precision = PRECISION[precision]
     p.riemann = RIEMANN[riemann]
-    p.emf = L.MHD_EMF_EC
+    p.emf = EMF[emf]
+    p.recon = RECON[recon]
     p.integrator = INTEGRATOR[integrator]
     p.tile, p.zchunk = int(tile), int(zchunk)
     return p
 
 
-def workspace_bytes(nx, ny, nz, precision="fp64", tile=0) -> int:
-    p = make_params(nx, ny, nz, precision=precision, tile=tile)
+def workspace_bytes(nx, ny, nz, precision="fp64", tile=0, integrator="rk2") -> int:
+    p = make_params(nx, ny, nz, precision=precision, tile=tile, integrator=integrator)
     return int(L.lib().mhd_workspace_bytes(C.byref(p)))
 
 
@@ -50,7 +54,8 @@ class MHDBox:
 
     def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, gamma=5.0 / 3.0, cfl=0.3,
                  precision="fp64", riemann="hlld", integrator="rk2", device="cuda:0",
-                 stream: torch.cuda.Stream | None = None, tile=0, zchunk=0):
+                 stream: torch.cuda.Stream | None = None, tile=0, zchunk=0, emf="ec",
+                 recon="plm"):
         self.lib = L.lib()
         self.device = torch.device(device)
         self.precision = precision
@@ -60,7 +65,7 @@ class MHDBox:
         # per-thread stream that the HIP null stream does not order against
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         p = make_params(nx, ny, nz, lx, ly, lz, gamma, cfl, precision, riemann, integrator, tile,
-                        zchunk)
+                        zchunk, emf, recon)
         nbytes = int(self.lib.mhd_workspace_bytes(C.byref(p)))
         if nbytes == 0:
             raise L.MHDError(L.MHD_ERR_INVALID_ARG, "mhd_workspace_bytes")

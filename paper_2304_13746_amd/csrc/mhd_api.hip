@@ -18,7 +18,8 @@ struct mhd_ctx {
   long long ncell;
   double idl[3];     // 1 / (l_d / n_d)
   double dv;         // cell volume
-  void* buf[2][8];   // two state buffers of 8 fields
+  void* buf[kMaxBuf][8];  // state buffers of 8 fields (3 for RK3, else 2)
+  int nbuf;
   int cur;           // buffer holding the state
   Scalars* sc;       // device scalars
   BoxDesc* desc;     // device copy of this box's descriptor
@@ -48,6 +49,9 @@ size_t field_bytes(const mhd_params* p) {
   size_t e = p->precision == MHD_FP32 ? 4 : 8;
   return align_up((size_t)p->nx * p->ny * p->nz * e);
 }
+
+// state buffers a context needs: U_0 and one per intermediate stage result
+int nbuf_of(const mhd_params* p) { return p->integrator == MHD_RK3 ? 3 : 2; }
 
 // ---- cycle control kernels (one thread): everything stays on the device
 
@@ -207,26 +211,41 @@ void fields_of(const mhd_state_view* v, void* out[8]) {
   out[4] = v->en; out[5] = v->bx; out[6] = v->by; out[7] = v->bz;
 }
 
-// One stage launch over n contexts sharing precision, solver and tile; src[i]
-// is the buffer box i reads.  Batches beyond kMaxBatch go out in chunks.
-hipError_t launch_stage(mhd_ctx* const* c, const int* src, int n, int mode, hipStream_t st) {
+// Stage roles of one box: the buffer S_dt acts on, the buffer written and, for a
+// combining stage, the buffer holding U_0.
+struct Roles {
+  unsigned char src, dst, base;
+};
+
+// One stage launch over n contexts sharing precision, solver and tile, with
+// weights (w, w0) for a combining stage.  Batches beyond kMaxBatch go out in
+// chunks.
+hipError_t launch_stage(mhd_ctx* const* c, const Roles* r, int n, int mode, double w, double w0,
+                        hipStream_t st) {
   for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
     const int m = n - i0 < kMaxBatch ? n - i0 : kMaxBatch;
     BatchArgs ba = {};
     ba.nbox = m;
     ba.mode = mode;
+    ba.w = w;
+    ba.w0 = w0;
+    ba.emf = c[i0]->p.emf;
     int g = 0;
     for (int i = 0; i < m; ++i) {
       ba.desc[i] = c[i0 + i]->desc;
       ba.start[i] = g;
-      ba.src[i] = (unsigned char)src[i0 + i];
+      ba.src[i] = r[i0 + i].src;
+      ba.dst[i] = r[i0 + i].dst;
+      ba.base[i] = r[i0 + i].base;
       g += c[i0 + i]->tiles;
     }
     ba.start[m] = g;
     ba.total = g;
     const mhd_ctx* c0 = c[i0];
-    hipError_t e = c0->p.precision == MHD_FP32 ? stage_f32(ba, c0->tile, c0->p.riemann, st, false)
-                                               : stage_f64(ba, c0->tile, c0->p.riemann, st, false);
+    const int rc = c0->p.recon;
+    hipError_t e = c0->p.precision == MHD_FP32
+                       ? stage_f32(ba, c0->tile, c0->p.riemann, rc, st, false)
+                       : stage_f64(ba, c0->tile, c0->p.riemann, rc, st, false);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -257,28 +276,39 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
   int maxs = 0;
   for (int i = 0; i < n; ++i) maxs = nsteps[i] > maxs ? nsteps[i] : maxs;
   if (maxs == 0) return MHD_OK;
-  mhd_ctx* act[4096];
-  int src[4096];
-  double ts[4096];
   if (n > 4096) return MHD_ERR_INVALID_ARG;
+  static thread_local mhd_ctx* act[4096];
+  static thread_local Roles roles[4096];
+  static thread_local double ts[4096];
   int m = 0;
   for (int i = 0; i < n; ++i)
     if (nsteps[i] > 0) { act[m] = c[i]; ts[m] = t_stop ? t_stop[i] : 0.0; ++m; }
   if (launch_ctl(true, act, m, ts, st) != hipSuccess) return MHD_ERR_HIP;
-  const bool rk2 = c[0]->p.integrator == MHD_RK2;
+  const int integ = c[0]->p.integrator;
   for (int cyc = 0; cyc < maxs; ++cyc) {
     m = 0;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > cyc) { act[m] = c[i]; ts[m] = t_stop ? t_stop[i] : 0.0; ++m; }
-    for (int i = 0; i < m; ++i) src[i] = act[i]->cur;
-    // U_1 = S_dt(U_0), measuring the next dt
-    if (launch_stage(act, src, m, 0, st) != hipSuccess) return MHD_ERR_HIP;
-    if (rk2) {
+    // stage 1: U_1 = S_dt(U_0), measuring the next dt (eq. cfl)
+    for (int i = 0; i < m; ++i) {
+      const int u0 = act[i]->cur;
+      roles[i] = {(unsigned char)u0, (unsigned char)(u0 == 0 ? 1 : 0), (unsigned char)u0};
+    }
+    if (launch_stage(act, roles, m, 0, 1.0, 0.0, st) != hipSuccess) return MHD_ERR_HIP;
+    if (integ == MHD_RK2) {
       // U^{n+1} = 1/2 S_dt(U_1) + 1/2 U_0, written over U_0
-      for (int i = 0; i < m; ++i) src[i] = 1 - act[i]->cur;
-      if (launch_stage(act, src, m, 1, st) != hipSuccess) return MHD_ERR_HIP;
+      for (int i = 0; i < m; ++i) roles[i] = {roles[i].dst, roles[i].src, roles[i].src};
+      if (launch_stage(act, roles, m, 1, 0.5, 0.5, st) != hipSuccess) return MHD_ERR_HIP;
+    } else if (integ == MHD_RK3) {
+      // U_2 = 1/4 S_dt(U_1) + 3/4 U_0 into the third buffer, then
+      // U^{n+1} = 2/3 S_dt(U_2) + 1/3 U_0 written over U_0 (cur is 0 here)
+      for (int i = 0; i < m; ++i) roles[i] = {1, 2, 0};
+      if (launch_stage(act, roles, m, 1, 0.25, 0.75, st) != hipSuccess) return MHD_ERR_HIP;
+      for (int i = 0; i < m; ++i) roles[i] = {2, 0, 0};
+      if (launch_stage(act, roles, m, 1, 2.0 / 3.0, 1.0 / 3.0, st) != hipSuccess)
+        return MHD_ERR_HIP;
     } else {
-      for (int i = 0; i < m; ++i) act[i]->cur = 1 - act[i]->cur;
+      for (int i = 0; i < m; ++i) act[i]->cur = roles[i].dst;
     }
     if (launch_ctl(false, act, m, ts, st) != hipSuccess) return MHD_ERR_HIP;
   }
@@ -306,12 +336,13 @@ int apply_shape(mhd_ctx* c, int tile, int zchunk) {
   if (!tile_dims(tile, &tx, &ty)) return MHD_ERR_INVALID_ARG;
   const mhd_params* p = &c->p;
   BatchArgs none = {};
-  hipError_t e = p->precision == MHD_FP32 ? stage_f32(none, tile, p->riemann, nullptr, true)
-                                          : stage_f64(none, tile, p->riemann, nullptr, true);
+  none.emf = p->emf;
+  hipError_t e = p->precision == MHD_FP32 ? stage_f32(none, tile, p->riemann, p->recon, nullptr, true)
+                                          : stage_f64(none, tile, p->riemann, p->recon, nullptr, true);
   if (e != hipSuccess) return MHD_ERR_HIP;
   const int lz = zchunk > 0 ? (zchunk < p->nz ? zchunk : p->nz) : choose_lz(tile, p->nx, p->ny, p->nz);
   BoxDesc d = {};
-  for (int b = 0; b < 2; ++b)
+  for (int b = 0; b < c->nbuf; ++b)
     for (int f = 0; f < 8; ++f) d.buf[b][f] = c->buf[b][f];
   d.nx = p->nx;
   d.ny = p->ny;
@@ -338,7 +369,8 @@ bool same_group(mhd_ctx* const* ctxs, int n) {
   for (int i = 1; i < n; ++i) {
     const mhd_ctx* c = ctxs[i];
     if (c->p.precision != c0->p.precision || c->p.riemann != c0->p.riemann ||
-        c->p.integrator != c0->p.integrator || c->tile != c0->tile || c->device != c0->device)
+        c->p.integrator != c0->p.integrator || c->p.emf != c0->p.emf ||
+        c->p.recon != c0->p.recon || c->tile != c0->tile || c->device != c0->device)
       return false;
   }
   return true;
@@ -365,7 +397,7 @@ size_t mhd_workspace_bytes(const mhd_params* p) {
   if (!grid_ok(p)) return 0;
   if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return 0;
   return align_up(sizeof(Scalars)) + align_up(sizeof(BoxDesc)) +
-         align_up(sizeof(double) * kDiagBlocks * kDiagVals) + 16 * field_bytes(p);
+         align_up(sizeof(double) * kDiagBlocks * kDiagVals) + 8 * nbuf_of(p) * field_bytes(p);
 }
 
 int mhd_create(const mhd_params* p, mhd_ctx** out) {
@@ -377,8 +409,11 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
     return MHD_ERR_INVALID_ARG;
   if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return MHD_ERR_INVALID_ARG;
   if (p->riemann != MHD_HLLD && p->riemann != MHD_HLL) return MHD_ERR_INVALID_ARG;
-  if (p->emf != MHD_EMF_EC) return MHD_ERR_UNSUPPORTED;
-  if (p->integrator != MHD_RK2 && p->integrator != MHD_EULER) return MHD_ERR_INVALID_ARG;
+  if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH)
+    return MHD_ERR_UNSUPPORTED;
+  if (p->recon != MHD_PLM && p->recon != MHD_LIMO3) return MHD_ERR_UNSUPPORTED;
+  if (p->integrator != MHD_RK2 && p->integrator != MHD_EULER && p->integrator != MHD_RK3)
+    return MHD_ERR_INVALID_ARG;
   if (p->zchunk < 0) return MHD_ERR_INVALID_ARG;
   int tile = p->tile == 0 ? default_tile(p->precision) : p->tile;
   int tx, ty;
@@ -408,8 +443,11 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   w += align_up(sizeof(BoxDesc));
   c->diag_part = (double*)w;
   w += align_up(sizeof(double) * kDiagBlocks * kDiagVals);
+  // buffers of 8 fields back to back with one field stride: the stage kernel
+  // relies on every buffer holding its fields at the same relative offsets
   const size_t fb = field_bytes(p);
-  for (int b = 0; b < 2; ++b)
+  c->nbuf = nbuf_of(p);
+  for (int b = 0; b < c->nbuf; ++b)
     for (int f = 0; f < 8; ++f) {
       c->buf[b][f] = w;
       w += fb;
@@ -445,8 +483,8 @@ int mhd_set_state(mhd_ctx* c, const mhd_state_view* v, double t, double dt_next)
   if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
   if (!(dt_next > 0.0)) {
     // eq. (cfl) on the initial state: the stage kernel in measuring mode
-    const int src0 = 0;
-    if (launch_stage(&c, &src0, 1, 2, c->stream) != hipSuccess) return MHD_ERR_HIP;
+    const Roles r0 = {0, 1, 0};
+    if (launch_stage(&c, &r0, 1, 2, 1.0, 0.0, c->stream) != hipSuccess) return MHD_ERR_HIP;
     hipLaunchKernelGGL(k_init_dt, dim3(1), dim3(1), 0, c->stream, c->sc);
     if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
   }
@@ -547,7 +585,7 @@ int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_resul
   static const int tiles[] = {TILE_24x8, TILE_16x16};
   static const int caps[] = {0, 8, 16, 32, 64, 128};
   const int ntile = sizeof(tiles) / sizeof(tiles[0]), ncap = sizeof(caps) / sizeof(caps[0]);
-  int* src = (int*)malloc(sizeof(int) * n);
+  Roles* src = (Roles*)malloc(sizeof(Roles) * n);
   float* times = (float*)malloc(sizeof(float) * reps);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = MHD_OK;
@@ -555,7 +593,10 @@ int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_resul
   if (rc == MHD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = MHD_ERR_HIP;
   for (int i = 0; i < n; ++i)
-    if (src) src[i] = ctxs[i]->cur;
+    if (src) {
+      const int u0 = ctxs[i]->cur;
+      src[i] = {(unsigned char)u0, (unsigned char)(u0 == 0 ? 1 : 0), (unsigned char)u0};
+    }
   const int def_tile = default_tile(ctxs[0]->p.precision);
   float best = 1e30f, def_ms = -1.0f;
   int best_tile = def_tile, best_cap = 0, tried = 0;
@@ -574,7 +615,7 @@ int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_resul
       if (rc != MHD_OK) break;
       // the first launch warms up; the median of the timed ones counts
       for (int r = 0; r <= reps && rc == MHD_OK; ++r) {
-        if (hipEventRecord(e0, st) != hipSuccess || launch_stage(ctxs, src, n, 0, st) != hipSuccess ||
+        if (hipEventRecord(e0, st) != hipSuccess || launch_stage(ctxs, src, n, 0, 1.0, 0.0, st) != hipSuccess ||
             hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
           rc = MHD_ERR_HIP;
           break;

@@ -46,6 +46,54 @@ __device__ __forceinline__ R van_leer(R dm, R dp) {
   return s > R(0) ? dvd(R(2) * s, dp + dm) : R(0);
 }
 
+// Reconstructions of Sec. 2.3: van Leer PLM, or the compact third-order LimO3
+// limiter of Cada & Torrilhon (2009), applied everywhere (its smooth-extremum
+// switch needs a problem length scale and is not used):
+//   upper face q + phi(dm/dp) dp / 2, lower face q - phi(dp/dm) dm / 2,
+//   phi(t) = max(0, min(p3, max(-t/2, min(2t, p3, 1.6)))), p3 = (2 + t)/3;
+// a zero difference leaves the face at the cell value.
+enum { RECON_PLM = 0, RECON_LIMO3 = 1 };
+
+template <typename R>
+__device__ __forceinline__ R limo3_phi(R th) {
+  R p3 = dvd(R(2) + th, R(3));
+  R inner = R(2) * th < p3 ? R(2) * th : p3;
+  inner = inner < R(1.6) ? inner : R(1.6);
+  R m = R(-0.5) * th > inner ? R(-0.5) * th : inner;
+  R r = p3 < m ? p3 : m;
+  return r > R(0) ? r : R(0);
+}
+
+// face values of cell q1 (neighbours q0 below, q2 above)
+template <int RECON, typename R>
+__device__ __forceinline__ R recon_hi(R q0, R q1, R q2) {
+  const R dm = q1 - q0, dp = q2 - q1;
+  if constexpr (RECON == RECON_LIMO3)
+    return dp == R(0) ? q1 : q1 + (R(0.5) * limo3_phi(dvd(dm, dp))) * dp;
+  else
+    return q1 + R(0.5) * van_leer(dm, dp);
+}
+template <int RECON, typename R>
+__device__ __forceinline__ R recon_lo(R q0, R q1, R q2) {
+  const R dm = q1 - q0, dp = q2 - q1;
+  if constexpr (RECON == RECON_LIMO3)
+    return dm == R(0) ? q1 : q1 - (R(0.5) * limo3_phi(dvd(dp, dm))) * dm;
+  else
+    return q1 - R(0.5) * van_leer(dm, dp);
+}
+// both faces of one cell (PLM shares its one limited slope)
+template <int RECON, typename R>
+__device__ __forceinline__ void recon_pair(R q0, R q1, R q2, R& lo, R& hi) {
+  if constexpr (RECON == RECON_LIMO3) {
+    lo = recon_lo<RECON>(q0, q1, q2);
+    hi = recon_hi<RECON>(q0, q1, q2);
+  } else {
+    const R sl = van_leer(q1 - q0, q2 - q1);
+    lo = q1 - R(0.5) * sl;
+    hi = q1 + R(0.5) * sl;
+  }
+}
+
 // Fast magnetosonic speed from a^2 = gamma p / rho, |B|^2 / rho and B_n^2 / rho.
 template <typename R>
 __device__ __forceinline__ R fast_speed(R gamma, R rho, R p, R bn, R b1, R b2) {
@@ -277,6 +325,12 @@ __device__ __forceinline__ void riemann(R gamma, R igm1, const Prim<R>& l, const
     flux_hlld(gamma, igm1, l, r, bn, f, cmax);
 }
 
+// Corner-EMF schemes of Sec. 2.4 (Gardiner & Stone 2005): E^c upwinds the
+// derivative terms by the sign of the face mass flux, E^0 averages the two
+// candidates on every side, the arithmetic scheme is the mean of the four face
+// EMFs alone.
+enum { EMF_EC = 0, EMF_E0 = 1, EMF_ARITH = 2 };
+
 // Upwind choice by the sign of a mass flux; zero averages the two candidates.
 template <typename R>
 __device__ __forceinline__ R upwind(R s, R l, R r) {
@@ -287,9 +341,11 @@ __device__ __forceinline__ R upwind(R s, R l, R r) {
 // a1, a2 are the P-face EMFs at (p-1/2, q), (p-1/2, q-1); b1, b2 the Q-face EMFs at
 // (p, q-1/2), (p-1, q-1/2); cAB the cell EMFs at (p-1+A, q-1+B); sq1, sq3 the
 // P-face and sp1, sp3 the Q-face mass fluxes next to a1, a2, b1, b2.
-template <typename R>
+template <int SCHEME, typename R>
 __device__ __forceinline__ R corner_emf(R a1, R a2, R b1, R b2, R c00, R c10, R c01, R c11, R sq1,
                                         R sq3, R sp1, R sp3) {
+  if constexpr (SCHEME == EMF_ARITH) return R(0.25) * ((a1 + a2) + (b1 + b2));
+  if constexpr (SCHEME == EMF_E0) sq1 = sq3 = sp1 = sp3 = R(0);  // every switch at its tie
   R dq1 = upwind(sq1, c01 - b2, c11 - b1);
   R dq3 = upwind(sq3, b2 - c00, b1 - c10);
   R dp1 = upwind(sp1, c10 - a2, c11 - a1);

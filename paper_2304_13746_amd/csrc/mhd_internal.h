@@ -52,9 +52,10 @@ __device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
 enum { TILE_16x16 = 1, TILE_24x8 = 2 };
 
 // One box as the stage kernel sees it; each context keeps its descriptor in its
-// own workspace (written once when the context is created).
+// own workspace (rewritten only when its launch shape changes).
+constexpr int kMaxBuf = 3;  // state buffers: U_0 and up to two stage results
 struct BoxDesc {
-  void* buf[2][8];        // two state buffers: rho mx my mz en bx by bz
+  void* buf[kMaxBuf][8];  // state buffers: rho mx my mz en bx by bz
   int nx, ny, nz;
   int ntx, nty, nzc, lz;  // tiles of the context's tile shape, z-chunks
   int pad;
@@ -64,20 +65,24 @@ struct BoxDesc {
 };
 
 // One stage launch over up to kMaxBatch boxes: global block g belongs to the
-// box b with start[b] <= g < start[b + 1]; src[b] is the buffer it reads
-// (it writes the other one).
+// box b with start[b] <= g < start[b + 1].  Box b applies S_dt to buffer
+// src[b] and writes buffer dst[b]; a combining stage writes
+// w S_dt(src) + w0 base with base = buffer base[b] (Sec. 2.7, Tab. weights).
 constexpr int kMaxBatch = 64;
 struct BatchArgs {
   int nbox, mode, total;
-  int pad;
+  int emf;  // corner-EMF scheme shared by the batch
+  double w, w0;
   const BoxDesc* desc[kMaxBatch];
   int start[kMaxBatch + 1];
-  unsigned char src[kMaxBatch];
+  unsigned char src[kMaxBatch], dst[kMaxBatch], base[kMaxBatch];
 };
 
 // stage launch for one precision (mhd_stage_f64.hip / mhd_stage_f32.hip)
-hipError_t stage_f64(const BatchArgs& b, int tile, int solver, hipStream_t st, bool prepare);
-hipError_t stage_f32(const BatchArgs& b, int tile, int solver, hipStream_t st, bool prepare);
+hipError_t stage_f64(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
+                     bool prepare);
+hipError_t stage_f32(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
+                     bool prepare);
 int tile_dims(int tile, int* tx, int* ty);
 
 }  // namespace mhd

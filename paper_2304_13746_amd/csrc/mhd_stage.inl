@@ -3,8 +3,9 @@
 // One launch applies the stage operator S_dt of Lesur et al. 2023 (Sec. 2.2-2.7,
 // steps S1 primitives, S2 reconstruction, S3 Riemann solves, S5 flux divergence,
 // S7 corner EMFs, S8 constrained-transport update) to a whole periodic box, and
-// either writes U* (first RK2 stage, Euler), writes 1/2 U* + 1/2 U_0 in place
-// over U_0 (second RK2 stage, Tab. weights), or only measures eq. (cfl).
+// either writes U* (first stage of a cycle), writes w U* + w0 U_0 (later
+// Runge-Kutta stages, Tab. weights; in place over U_0 for the last one), or only
+// measures eq. (cfl).
 //
 // Design (2.5D tile, z-march).  A thread block owns a TX x TY column tile of
 // cells and marches one z-chunk.  Each of its TX*TY + 2(TX+TY) threads owns one
@@ -31,7 +32,9 @@ namespace mhd {
 template <typename R>
 struct StageArgs {
   const R* src[8];  // state the operator acts on: rho mx my mz en bx by bz
-  R* dst[8];        // output state (second RK2 stage: also holds U_0)
+  R* dst[8];        // output state
+  long long boff;   // U_0 of a combining stage: element offset from dst (0: in place)
+  R w, w0;          // stage weights of a combining stage
   int nx, ny, nz;
   int ntx, nty, nzc, lz;  // tiles in x, y; z-chunks and their length
   R idl[3];  // 1 / dl_d
@@ -40,7 +43,7 @@ struct StageArgs {
   Scalars* scw;
 };
 
-enum { MODE_STAGE1 = 0, MODE_STAGE2 = 1, MODE_MEASURE = 2 };
+enum { MODE_STAGE1 = 0, MODE_COMBINE = 1, MODE_MEASURE = 2 };
 
 // State arrays live in global memory; loads and stores through these helpers
 // use global (not flat) instructions.
@@ -256,7 +259,7 @@ struct Occupancy {
   static constexpr int waves = sizeof(R) == 4 ? MHD_WAVES_F32 : MHD_WAVES_F64;
 };
 
-template <typename R, int SOLVER, int MODE, int TX, int TY>
+template <typename R, int SOLVER, int RECON, int EMF, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY + 2 * (TX + TY))
 __attribute__((amdgpu_waves_per_eu(Occupancy<R>::waves)))
 stage_kernel(BatchArgs ba) {
@@ -281,11 +284,17 @@ stage_kernel(BatchArgs ba) {
   StageArgs<R> a;
   {
     const BoxDesc* d = ba.desc[box];
-    const int si = ba.src[box];
+    const int si = ba.src[box], di = ba.dst[box], bi = ba.base[box];
     for (int f = 0; f < 8; ++f) {
       a.src[f] = static_cast<const R*>(d->buf[si][f]);
-      a.dst[f] = static_cast<R*>(d->buf[1 - si][f]);
+      a.dst[f] = static_cast<R*>(d->buf[di][f]);
     }
+    // every buffer holds its 8 fields at the same relative offsets, so U_0 sits
+    // at one fixed element offset from the output (a single scalar instead of
+    // eight more pointers)
+    a.boff = (static_cast<const R*>(d->buf[bi][0]) - static_cast<const R*>(d->buf[di][0]));
+    a.w = (R)ba.w;
+    a.w0 = (R)ba.w0;
     a.nx = d->nx; a.ny = d->ny; a.nz = d->nz;
     a.ntx = d->ntx; a.nty = d->nty; a.nzc = d->nzc; a.lz = d->lz;
     for (int k = 0; k < 3; ++k) a.idl[k] = (R)d->idl[k];
@@ -402,10 +411,8 @@ stage_kernel(BatchArgs ba) {
       R ql[7], qr[7];
 #pragma unroll
       for (int v = 0; v < 7; ++v) {
-        R sl = van_leer(q[1][v] - q[0][v], q[2][v] - q[1][v]);
-        R sr = van_leer(q[2][v] - q[1][v], q[3][v] - q[2][v]);
-        ql[v] = q[1][v] + R(0.5) * sl;
-        qr[v] = q[2][v] - R(0.5) * sr;
+        ql[v] = recon_hi<RECON>(q[0][v], q[1][v], q[2][v]);
+        qr[v] = recon_lo<RECON>(q[1][v], q[2][v], q[3][v]);
       }
       R bn;
       if (corner_x) {
@@ -443,10 +450,8 @@ stage_kernel(BatchArgs ba) {
       R ql[7], qr[7];
 #pragma unroll
       for (int v = 0; v < 7; ++v) {
-        R sl = van_leer(q[1][v] - q[0][v], q[2][v] - q[1][v]);
-        R sr = van_leer(q[2][v] - q[1][v], q[3][v] - q[2][v]);
-        ql[v] = q[1][v] + R(0.5) * sl;
-        qr[v] = q[2][v] - R(0.5) * sr;
+        ql[v] = recon_hi<RECON>(q[0][v], q[1][v], q[2][v]);
+        qr[v] = recon_lo<RECON>(q[1][v], q[2][v], q[3][v]);
       }
       R bn;
       if (corner_y) {
@@ -506,9 +511,10 @@ stage_kernel(BatchArgs ba) {
       R bot[7];
 #pragma unroll
       for (int v = 0; v < 7; ++v) {
-        R s = van_leer(qb[v] - qa[v], qc[v] - qb[v]);
-        bot[v] = qb[v] - R(0.5) * s;
-        qa[v] = qb[v] + R(0.5) * s;  // becomes top of cell m
+        R lo, hi;
+        recon_pair<RECON>(qa[v], qb[v], qc[v], lo, hi);
+        bot[v] = lo;
+        qa[v] = hi;  // becomes top of cell m
       }
       if (m >= z0) solve_face<2, SOLVER>(a, top7, bot, bz_m, fz);
 #pragma unroll
@@ -550,19 +556,19 @@ stage_kernel(BatchArgs ba) {
     R ez_new = 0, ex_new = 0, ey_new = 0;
     if (do_ez && m >= z0 && m < z1) {
       const int e_s = T::e(ci, cj - 1), e_w = T::e(ci - 1, cj), e_sw = T::e(ci - 1, cj - 1);
-      ez_new = corner_emf(S.xez[ex_me], S.xez[e_s], S.yez[ex_me], S.yez[e_w], S.erz[e_sw],
+      ez_new = corner_emf<EMF>(S.xez[ex_me], S.xez[e_s], S.yez[ex_me], S.yez[e_w], S.erz[e_sw],
                           S.erz[e_s], S.erz[e_w], S.erz[ex_me], S.xmass[ex_me], S.xmass[e_s],
                           S.ymass[ex_me], S.ymass[e_w]);
     }
     if (m >= z0) {
       if (do_ex) {
         const int e_s = T::e(ci, cj - 1);
-        ex_new = corner_emf(yex_now, yex_prev, fz.fb2, S.zex[e_s], S.erxp[e_s], erx_prev,
+        ex_new = corner_emf<EMF>(yex_now, yex_prev, fz.fb2, S.zex[e_s], S.erxp[e_s], erx_prev,
                             S.erx[e_s], erx, ymass_now, ymass_prev, fz.cons[0], S.zmass[e_s]);
       }
       if (do_ey) {
         const int e_w = T::e(ci - 1, cj);
-        ey_new = corner_emf(-fz.fb1, S.zey[e_w], xey_now, xey_prev, S.eryp[e_w], S.ery[e_w], ery_prev,
+        ey_new = corner_emf<EMF>(-fz.fb1, S.zey[e_w], xey_now, xey_prev, S.eryp[e_w], S.ery[e_w], ery_prev,
                             ery, fz.cons[0], S.zmass[e_w], xmass_now, xmass_prev);
       }
     }
@@ -575,7 +581,7 @@ stage_kernel(BatchArgs ba) {
       for (int q = 0; q < 5; ++q)
         part_new[q] = (gld(a.src[q], (long long)km * plane + col) - tau_x * (S.xcons[q][e_e] - S.xcons[q][ex_me])) -
                       tau_y * (S.ycons[q][e_n] - S.ycons[q][ex_me]);
-      if constexpr (MODE != MODE_STAGE2) {
+      if constexpr (MODE != MODE_COMBINE) {
         R cx = S.xcmax[ex_me] > S.xcmax[e_e] ? S.xcmax[ex_me] : S.xcmax[e_e];
         R cy = S.ycmax[ex_me] > S.ycmax[e_n] ? S.ycmax[ex_me] : S.ycmax[e_n];
         cxy_new = cx * a.idl[0] + cy * a.idl[1];
@@ -584,7 +590,7 @@ stage_kernel(BatchArgs ba) {
     // finalise cell m-1: z-flux difference, stage combination, face B
     if (real && m - 1 >= z0 && m <= z1) {
       const long long o = (long long)wrapi(m - 1, a.nz) * plane + col;
-      if constexpr (MODE != MODE_STAGE2) {
+      if constexpr (MODE != MODE_COMBINE) {
         R cz = zc_prev > fz.cmax ? zc_prev : fz.cmax;
         R inv = cxy_prev + cz * a.idl[2];
         inv_max = inv > inv_max ? inv : inv_max;
@@ -596,11 +602,11 @@ stage_kernel(BatchArgs ba) {
         const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
         R bxn = (gld(a.src[5], o) - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
         R byn = (gld(a.src[6], o) - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
-        if constexpr (MODE == MODE_STAGE2) {
+        if constexpr (MODE == MODE_COMBINE) {
 #pragma unroll
-          for (int q = 0; q < 5; ++q) un[q] = R(0.5) * un[q] + R(0.5) * gld<R>(a.dst[q], o);
-          bxn = R(0.5) * bxn + R(0.5) * gld<R>(a.dst[5], o);
-          byn = R(0.5) * byn + R(0.5) * gld<R>(a.dst[6], o);
+          for (int q = 0; q < 5; ++q) un[q] = a.w * un[q] + a.w0 * gld<R>(a.dst[q], o + a.boff);
+          bxn = a.w * bxn + a.w0 * gld<R>(a.dst[5], o + a.boff);
+          byn = a.w * byn + a.w0 * gld<R>(a.dst[6], o + a.boff);
         }
 #pragma unroll
         for (int q = 0; q < 5; ++q) gst(a.dst[q], o, un[q]);
@@ -620,7 +626,7 @@ stage_kernel(BatchArgs ba) {
         const long long o = (long long)km * plane + col;
         const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
         R bzn = (bz_m - tau_x * (S.ey[e_e] - ey_new)) + tau_y * (S.ex[e_n] - ex_new);
-        if constexpr (MODE == MODE_STAGE2) bzn = R(0.5) * bzn + R(0.5) * gld<R>(a.dst[7], o);
+        if constexpr (MODE == MODE_COMBINE) bzn = a.w * bzn + a.w0 * gld<R>(a.dst[7], o + a.boff);
         gst(a.dst[7], o, bzn);
       }
     }
@@ -646,7 +652,7 @@ stage_kernel(BatchArgs ba) {
   }
 
   // ---- block results: CFL maximum and status
-  if constexpr (MODE != MODE_STAGE2) {
+  if constexpr (MODE != MODE_COMBINE) {
     R v = inv_max;
     for (int off = 32; off > 0; off >>= 1) {
       R o = __shfl_xor(v, off);
@@ -662,12 +668,12 @@ stage_kernel(BatchArgs ba) {
 
 
 // Launch one instantiation.  With prepare = true only raise its dynamic-LDS
-// limit (a host-side attribute, done once when a context is created).
-template <typename R, int SOLVER, int MODE, int TX, int TY>
+// limit (a host-side attribute, done when a context takes a launch shape).
+template <typename R, int SOLVER, int RECON, int EMF, int MODE, int TX, int TY>
 static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) {
   using T = Tile<TX, TY>;
   const size_t lds = sizeof(SmemAll<R, TX, TY>);
-  auto fn = stage_kernel<R, SOLVER, MODE, TX, TY>;
+  auto fn = stage_kernel<R, SOLVER, RECON, EMF, MODE, TX, TY>;
   if (prepare)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -675,25 +681,40 @@ static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) 
   return hipGetLastError();
 }
 
-template <typename R, int TX, int TY>
-static hipError_t launch_tile(const BatchArgs& ba, int solver, hipStream_t st, bool prepare) {
-  const int mode = ba.mode;
-  if (solver == 0) {
-    if (mode == MODE_STAGE1) return launch_one<R, 0, MODE_STAGE1, TX, TY>(ba, st, prepare);
-    if (mode == MODE_STAGE2) return launch_one<R, 0, MODE_STAGE2, TX, TY>(ba, st, prepare);
-    return launch_one<R, 0, MODE_MEASURE, TX, TY>(ba, st, prepare);
-  }
-  if (mode == MODE_STAGE1) return launch_one<R, 1, MODE_STAGE1, TX, TY>(ba, st, prepare);
-  if (mode == MODE_STAGE2) return launch_one<R, 1, MODE_STAGE2, TX, TY>(ba, st, prepare);
-  return launch_one<R, 1, MODE_MEASURE, TX, TY>(ba, st, prepare);
+template <typename R, int SOLVER, int RECON, int EMF, int TX, int TY>
+static hipError_t launch_mode(const BatchArgs& ba, hipStream_t st, bool prepare) {
+  if (ba.mode == MODE_STAGE1)
+    return launch_one<R, SOLVER, RECON, EMF, MODE_STAGE1, TX, TY>(ba, st, prepare);
+  if (ba.mode == MODE_COMBINE)
+    return launch_one<R, SOLVER, RECON, EMF, MODE_COMBINE, TX, TY>(ba, st, prepare);
+  return launch_one<R, SOLVER, RECON, EMF, MODE_MEASURE, TX, TY>(ba, st, prepare);
+}
+
+template <typename R, int SOLVER, int RECON, int TX, int TY>
+static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) {
+  if (ba.emf == EMF_E0) return launch_mode<R, SOLVER, RECON, EMF_E0, TX, TY>(ba, st, prepare);
+  if (ba.emf == EMF_ARITH) return launch_mode<R, SOLVER, RECON, EMF_ARITH, TX, TY>(ba, st, prepare);
+  return launch_mode<R, SOLVER, RECON, EMF_EC, TX, TY>(ba, st, prepare);
 }
 
 template <typename R, int TX, int TY>
-static hipError_t prepare_tile(int solver) {
+static hipError_t launch_tile(const BatchArgs& ba, int solver, int recon, hipStream_t st,
+                              bool prepare) {
+  if (solver == 0)
+    return recon == RECON_LIMO3 ? launch_emf<R, 0, RECON_LIMO3, TX, TY>(ba, st, prepare)
+                                : launch_emf<R, 0, RECON_PLM, TX, TY>(ba, st, prepare);
+  return recon == RECON_LIMO3 ? launch_emf<R, 1, RECON_LIMO3, TX, TY>(ba, st, prepare)
+                              : launch_emf<R, 1, RECON_PLM, TX, TY>(ba, st, prepare);
+}
+
+// Raise the LDS limit of every mode of one (solver, reconstruction, EMF) choice.
+template <typename R, int TX, int TY>
+static hipError_t prepare_tile(int solver, int recon, int emf) {
   BatchArgs ba = {};
+  ba.emf = emf;
   for (int mode = 0; mode < 3; ++mode) {
     ba.mode = mode;
-    hipError_t e = launch_tile<R, TX, TY>(ba, solver, nullptr, true);
+    hipError_t e = launch_tile<R, TX, TY>(ba, solver, recon, nullptr, true);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

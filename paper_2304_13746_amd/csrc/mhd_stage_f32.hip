@@ -2,7 +2,8 @@
 #include "mhd_stage.inl"
 #include "mhd_stage_launch.inl"
 namespace mhd {
-hipError_t stage_f32(const BatchArgs& b, int tile, int solver, hipStream_t st, bool prepare) {
-  return stage_launch<float>(b, tile, solver, st, prepare);
+hipError_t stage_f32(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
+                     bool prepare) {
+  return stage_launch<float>(b, tile, solver, recon, st, prepare);
 }
 }  // namespace mhd

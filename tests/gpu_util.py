@@ -27,11 +27,13 @@ def gpu_box(dims, l=(1.0, 1.0, 1.0), precision="fp64", riemann="hlld", integrato
 
 
 def oracle_params(dims, l=(1.0, 1.0, 1.0), riemann="hlld", integrator="rk2", gamma=5.0 / 3.0,
-                  cfl=0.3):
+                  cfl=0.3, emf="ec", recon="plm"):
     nx, ny, nz = dims
     return O.Params(nx, ny, nz, *l, gamma=gamma, cfl=cfl,
                     riemann={"hlld": O.HLLD, "hll": O.HLL}[riemann],
-                    integrator={"rk2": O.RK2, "euler": O.EULER}[integrator])
+                    integrator={"rk2": O.RK2, "euler": O.EULER, "rk3": O.RK3}[integrator],
+                    emf={"ec": O.EMF_EC, "e0": O.EMF_E0, "arith": O.EMF_ARITH}[emf],
+                    recon={"plm": O.PLM, "limo3": O.LIMO3}[recon])
 
 
 def run_both(state, dims, nsteps, l=(1.0, 1.0, 1.0), riemann="hlld", precision="fp64",
@@ -41,7 +43,8 @@ def run_both(state, dims, nsteps, l=(1.0, 1.0, 1.0), riemann="hlld", precision="
     box = gpu_box(dims, l, precision=precision, riemann=riemann, integrator=integrator, **kw)
     box.set_state(state, 0.0, 0.0)
     orc = O.copy_state(state)
-    p = oracle_params(dims, l, riemann, integrator)
+    p = oracle_params(dims, l, riemann, integrator, emf=kw.get("emf", "ec"),
+                      recon=kw.get("recon", "plm"))
     gd, od = [], []
     t, dt = 0.0, 0.0
     if per_step:
@@ -79,3 +82,81 @@ def max_rel(g, o):
 
 def bit_equal(g, o):
     return all(np.array_equal(g[f], o[f]) for f in FIELDS)
+
+
+# ---- FP32 comparisons near E^c upwind ties
+#
+# The E^c corner EMF (Sec. 2.4) upwinds by the sign of the face mass flux, a
+# discontinuous choice.  Where that flux is within FP32 rounding of zero, an
+# FP32 run may take the other (equally valid) side than the FP64 oracle, and
+# the face fields around that edge then differ by the jump between the two
+# one-sided derivatives instead of by rounding.  Fluid variables do not see
+# the choice in the stage that makes it.  FP32 checks therefore mark the
+# cells within TIE_DILATE cells of any face whose stage-input mass flux is
+# below TIE_REL times the largest one, hold the face fields there to a looser
+# bound, and require such cells to be rare.
+
+TIE_REL = 1e-5
+TIE_DILATE = 2
+TIE_LOOSE = 1e-2
+TIE_MAX_FRACTION = 0.05
+STAGE_WEIGHTS = {"rk2": [(1.0, 0.0), (0.5, 0.5)], "euler": [(1.0, 0.0)],
+                 "rk3": [(1.0, 0.0), (0.25, 0.75), (2.0 / 3.0, 1.0 / 3.0)]}
+
+
+def _dilate(mask, r):
+    out = mask.copy()
+    for ax in range(3):
+        cur = out.copy()
+        for sft in range(1, r + 1):
+            cur |= np.roll(out, sft, axis=ax) | np.roll(out, -sft, axis=ax)
+        out = cur
+    return out
+
+
+def upwind_tie_cells(p, s, dt, integrator="rk2"):
+    """Cells near faces whose E^c upwind choice, in any stage of one cycle of
+    step dt from s, rests on a mass flux within FP32 rounding of zero."""
+    pe = O.Params(p.nx, p.ny, p.nz, p.lx, p.ly, p.lz, gamma=p.gamma, riemann=p.riemann,
+                  integrator=O.EULER)
+    stage_inputs = [s]
+    prev = s
+    for ws, w0 in STAGE_WEIGHTS[integrator][:-1]:
+        star = O.copy_state(prev)
+        O.step(pe, star, 0.0, dt, 1)
+        prev = {f: ws * star[f] + w0 * s[f] for f in FIELDS}
+        stage_inputs.append(prev)
+    tie = np.zeros((p.nz, p.ny, p.nx), dtype=bool)
+    for u in stage_inputs:
+        fl = O.mass_flux(p, u)
+        scale = max(float(np.max(np.abs(a))) for a in fl)
+        for a in fl:
+            # exact zeros come from symmetry (e.g. v_z = 0 everywhere), which an
+            # FP32 run reproduces exactly: no ambiguity there
+            tie |= (np.abs(a) <= TIE_REL * scale) & (a != 0.0)
+    return _dilate(tie, TIE_DILATE)
+
+
+def fp32_errors(g, o, near):
+    """Norm-wise relative errors per group; face fields split into cells away
+    from upwind ties and near them."""
+    out = {}
+    for grp in GROUPS:
+        den = max(max(float(np.max(np.abs(o[f]))) for f in grp), 1e-300)
+        if grp[0] != "bx":
+            out[grp[0]] = max(float(np.max(np.abs(g[f] - o[f]))) for f in grp) / den
+            continue
+        far = ~near
+        out["b_far"] = max(float(np.max(np.abs(g[f] - o[f])[far], initial=0.0)) for f in grp) / den
+        out["b_near"] = max(float(np.max(np.abs(g[f] - o[f])[near], initial=0.0)) for f in grp) / den
+    out["near_fraction"] = float(np.mean(near))
+    return out
+
+
+def assert_fp32_close(g, o, near, tol=1e-5):
+    e = fp32_errors(g, o, near)
+    for k in ("rho", "mx", "en", "b_far"):
+        assert e[k] <= tol, e
+    assert e["b_near"] <= TIE_LOOSE, e
+    assert e["near_fraction"] <= TIE_MAX_FRACTION, e
+    return e

@@ -73,3 +73,29 @@ def test_graph_replay_matches_eager():
             g, t, dt, _ = bx.get_state_numpy()
             e, te, de, _ = r.get_state_numpy()
             assert bit_equal(g, e) and t == te and dt == de, rep
+
+
+def test_rk3_batch_and_graph_match_alone():
+    """RK3 boxes: a batch equals each box alone, and a captured graph replays
+    the eager result (FP64, bit for bit)."""
+    torch = need_gpu()
+    from paper_2304_13746_amd.batch import BoxBatch
+    from paper_2304_13746_amd.box import MHDBox
+    spec = small_batch(4, seed=9)
+    stream = torch.cuda.Stream()
+    boxes = []
+    for sp in spec:
+        bx = MHDBox(*sp["dims"], *sp["l"], integrator="rk3", stream=stream)
+        bx.set_state(sp["state"])
+        boxes.append(bx)
+    graph = BoxBatch(boxes).capture(2)
+    for _ in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+    for sp, bx in zip(spec, boxes):
+        alone = MHDBox(*sp["dims"], *sp["l"], integrator="rk3")
+        alone.set_state(sp["state"])
+        alone.step(4)
+        a, ta, da, _ = alone.get_state_numpy()
+        g, t, dt, _ = bx.get_state_numpy()
+        assert bit_equal(a, g) and ta == t and da == dt, sp["dims"]

@@ -4,7 +4,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import FIELDS, bit_equal, gpu_box, max_rel, need_gpu, run_both
+from gpu_util import (FIELDS, assert_fp32_close, bit_equal, gpu_box, max_rel, need_gpu, run_both,
+                      upwind_tie_cells)
 from paper_2304_13746_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -28,12 +29,16 @@ def test_full_size_256_fp64_bit_exact(turb256):
 
 
 def test_full_size_256_fp32(turb256):
+    """One FP32 cycle at 256^3 against the FP64 oracle on the rounded input:
+    1e-5 norm-wise relative, face fields near E^c upwind ties to the looser
+    bound (see gpu_util)."""
     need_gpu()
     s = I.to_float32_exact(turb256)
     g, o, gd, od, _ = run_both(s, (256, 256, 256), 1, precision="fp32")
-    err = max_rel(g, o)
-    print("256^3 fp32 max rel", err)
-    assert err <= 1e-5
+    p = O.Params(256, 256, 256)
+    near = upwind_tie_cells(p, s, 0.3 / O.max_invdt(p, s))
+    e = assert_fp32_close(g, o, near)
+    print("256^3 fp32 errors", e, "max rel", max_rel(g, o))
     assert abs(gd[-1] - od[-1]) <= 1e-5 * od[-1]
 
 

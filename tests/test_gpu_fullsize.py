@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import FIELDS, bit_equal, max_rel, need_gpu
+from gpu_util import FIELDS, assert_fp32_close, bit_equal, max_rel, need_gpu, upwind_tie_cells
 from helpers import inner, oracle_window_cycle, take_window, window_index
 from paper_2304_13746_amd import inputs as I
 
@@ -82,7 +82,10 @@ def test_c5_512_one_cycle_sampled(c5_state, precision):
         if precision == "fp64":
             assert bit_equal(got, ref), c
         else:
-            assert err <= 1e-5, (c, err)
+            w = take_window(s, idx)
+            pw = O.Params(WIN, WIN, WIN, WIN / N5, WIN / N5, WIN / N5)
+            near = inner({"m": upwind_tie_cells(pw, w, t)})["m"]
+            assert_fp32_close(got, ref, near)
     print(f"512^3 {precision}: worst window max rel {worst:.3e}")
     box.close()
 
@@ -150,8 +153,8 @@ def test_c3_batch_full_size_vs_oracle(precision):
         if precision == "fp64":
             assert bit_equal(g, o) and t == to, sp["dims"]
         else:
-            err = max_rel(g, o)
-            worst = max(worst, err)
-            assert err <= 1e-5, (sp["dims"], err)
+            near = upwind_tie_cells(p, st, to)
+            e = assert_fp32_close(g, o, near)
+            worst = max(worst, e["b_near"], e["b_far"], e["rho"], e["mx"], e["en"])
             assert abs(t - to) <= 1e-5 * to
     print(f"64 boxes {precision}: worst max rel {worst:.3e}")

@@ -113,3 +113,74 @@ def test_linear_wave_gpu_matches_oracle():
     g, tg, _, _ = box.get_state_numpy()
     assert tg == pytest.approx(tc, rel=1e-14)
     assert bit_equal(g, o)
+
+
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+def test_rk3_fp64_bit_exact(riemann):
+    """Third-order Runge-Kutta cycle (Tab. weights: 1, 1/4 + 3/4 U_0, 2/3 + 1/3
+    U_0; three state buffers) on a ragged turbulent box: bit-identical to the
+    oracle, dt sequence included."""
+    need_gpu()
+    dims = (40, 24, 18)
+    s = I.turbulence(dims, seed=13, kpeak=2.0, mach=1.0, b0=(0.2, -0.3, 0.1))
+    l = s.pop("_l")
+    g, o, gd, od, (tg, to) = run_both(s, dims, 4, l=l, riemann=riemann, integrator="rk3",
+                                      per_step=True)
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+
+
+def test_rk3_fp32_within_tolerance():
+    need_gpu()
+    s = I.to_float32_exact(I.orszag_tang(32))
+    g, o, gd, od, _ = run_both(s, (32, 32, 32), 5, integrator="rk3", precision="fp32")
+    err = max_rel(g, o)
+    print("rk3 fp32 max rel", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("emf", ["e0", "arith"])
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+def test_emf_schemes_fp64_bit_exact(emf, riemann):
+    """E^0 and arithmetic corner EMFs (Sec. 2.4) on a ragged turbulent box, RK2:
+    bit-identical to the oracle with the same scheme."""
+    need_gpu()
+    dims = (40, 24, 18)
+    s = I.turbulence(dims, seed=17, kpeak=2.0, mach=1.0, b0=(0.3, 0.2, -0.1))
+    l = s.pop("_l")
+    g, o, gd, od, (tg, to) = run_both(s, dims, 4, l=l, riemann=riemann, per_step=True, emf=emf)
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+
+
+def test_emf_scheme_fp32_within_tolerance():
+    need_gpu()
+    s = I.to_float32_exact(I.orszag_tang(32))
+    for emf in ("e0", "arith"):
+        g, o, _, _, _ = run_both(s, (32, 32, 32), 5, precision="fp32", emf=emf)
+        assert max_rel(g, o) <= 1e-5, emf
+
+
+@pytest.mark.parametrize("integrator", ["rk2", "rk3"])
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+def test_limo3_fp64_bit_exact(riemann, integrator):
+    """LimO3 reconstruction (Sec. 2.3) on a ragged turbulent box: bit-identical
+    to the oracle with the same reconstruction, alone and with RK3."""
+    need_gpu()
+    dims = (40, 24, 18)
+    s = I.turbulence(dims, seed=19, kpeak=2.0, mach=1.0, b0=(0.2, -0.1, 0.3))
+    l = s.pop("_l")
+    g, o, gd, od, (tg, to) = run_both(s, dims, 4, l=l, riemann=riemann, integrator=integrator,
+                                      per_step=True, recon="limo3")
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+
+
+def test_limo3_fp32_within_tolerance():
+    need_gpu()
+    s = I.to_float32_exact(I.orszag_tang(32))
+    g, o, _, _, _ = run_both(s, (32, 32, 32), 5, precision="fp32", recon="limo3",
+                             integrator="rk3")
+    err = max_rel(g, o)
+    print("limo3 fp32 max rel", err)
+    assert err <= 1e-5
