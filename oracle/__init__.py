@@ -24,9 +24,10 @@ SRC = os.path.join(HERE, "mhd_oracle.c")
 LIB = os.path.join(HERE, "libmhd_oracle.so")
 FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
 
-HLLD, HLL = 0, 1
+HLLD, HLL, HLLC = 0, 1, 2
 RK2, EULER, RK3 = 0, 1, 2
 EMF_EC, EMF_E0, EMF_ARITH = 0, 1, 2
+PLM, LIMO3 = 0, 1
 OK, ERR_INVALID_ARG, ERR_NOMEM, ERR_NONPHYSICAL = 0, -1, -2, -4
 
 # -ffp-contract=off: no fused multiply-add, every expression rounds as written.
@@ -47,7 +48,8 @@ class _Params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
                 ("gamma", C.c_double), ("cfl", C.c_double),
-                ("riemann", C.c_int), ("integrator", C.c_int), ("emf", C.c_int)]
+                ("riemann", C.c_int), ("integrator", C.c_int), ("emf", C.c_int),
+                ("recon", C.c_int)]
 
 
 class _State(C.Structure):
@@ -73,6 +75,9 @@ def lib():
         L.orc_mass_flux.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, dp]
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
         L.orc_vanleer.restype = C.c_double
+        L.orc_limo3_phi.argtypes = [C.c_double]
+        L.orc_limo3_phi.restype = C.c_double
+        L.orc_recon.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp]
         for fn in (L.orc_fast_speed, L.orc_slow_speed):
             fn.argtypes = [C.c_double] * 6
             fn.restype = C.c_double
@@ -100,10 +105,11 @@ class Params:
     riemann: int = HLLD
     integrator: int = RK2
     emf: int = EMF_EC
+    recon: int = PLM
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.gamma,
-                       self.cfl, self.riemann, self.integrator, self.emf)
+                       self.cfl, self.riemann, self.integrator, self.emf, self.recon)
 
 
 def _dptr(a: np.ndarray):
@@ -164,6 +170,17 @@ def diagnostics(p: Params, s: dict) -> dict:
 
 def vanleer(dm: float, dp: float) -> float:
     return lib().orc_vanleer(dm, dp)
+
+
+def limo3_phi(theta: float) -> float:
+    return lib().orc_limo3_phi(theta)
+
+
+def recon(kind: int, q0: float, q1: float, q2: float):
+    """(lower, upper) face values of cell q1 between q0 and q2."""
+    lo, hi = C.c_double(), C.c_double()
+    lib().orc_recon(kind, q0, q1, q2, C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
 
 
 def fast_speed(gamma, rho, p, bn, bt1, bt2) -> float:

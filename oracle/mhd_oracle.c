@@ -12,10 +12,12 @@
  *   S1  conserved -> primitive variables; cell-centred B is the mean of the two
  *       faces (the face-to-cell rule of Sec. 3.3 output).
  *   S2  piecewise-linear reconstruction of (rho, v, B_t, p) with the van Leer
- *       limiter (Sec. 2.3); B_n on a face is the staggered face value (Sec. 2.4).
+ *       limiter, or the LimO3 third-order reconstruction (Sec. 2.3); B_n on a
+ *       face is the staggered face value (Sec. 2.4).
  *   S3  HLL (Einfeldt et al. 1991) or HLLD (Miyoshi & Kusano 2005) flux on every
- *       x, y, z face; pressure is inside the momentum flux (Sec. 2.3).  The same
- *       solve yields c_max for the CFL condition (eq. cfl).
+ *       x, y, z face, or HLLC (Toro et al. 1994) for B = 0 problems; pressure is
+ *       inside the momentum flux (Sec. 2.3).  The same solve yields c_max for
+ *       the CFL condition (eq. cfl).
  *   S5  conservative update of (rho, m, E) by the flux divergence (eq. gal).
  *   S7  corner EMFs with the upwind-by-contact scheme E^c of Gardiner & Stone
  *       (2005), the default of Sec. 2.4, or its E^0 and arithmetic variants.
@@ -48,6 +50,7 @@ typedef struct {
   double dv;     /* cell volume */
   int riemann;
   int emf;
+  int recon;
 } grid_t;
 
 static void grid_init(grid_t* g, const orc_params* p) {
@@ -65,17 +68,20 @@ static void grid_init(grid_t* g, const orc_params* p) {
   g->dv = (dx * dy) * dz;
   g->riemann = p->riemann;
   g->emf = p->emf;
+  g->recon = p->recon;
 }
 
 static int check_params(const orc_params* p) {
   if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return ORC_ERR_INVALID_ARG;
   if (!(p->lx > 0) || !(p->ly > 0) || !(p->lz > 0)) return ORC_ERR_INVALID_ARG;
   if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || !(p->cfl < 1.0)) return ORC_ERR_INVALID_ARG;
-  if (p->riemann != ORC_HLLD && p->riemann != ORC_HLL) return ORC_ERR_INVALID_ARG;
+  if (p->riemann != ORC_HLLD && p->riemann != ORC_HLL && p->riemann != ORC_HLLC)
+    return ORC_ERR_INVALID_ARG;
   if (p->integrator != ORC_RK2 && p->integrator != ORC_EULER && p->integrator != ORC_RK3)
     return ORC_ERR_INVALID_ARG;
   if (p->emf != ORC_EMF_EC && p->emf != ORC_EMF_E0 && p->emf != ORC_EMF_ARITH)
     return ORC_ERR_INVALID_ARG;
+  if (p->recon != ORC_PLM && p->recon != ORC_LIMO3) return ORC_ERR_INVALID_ARG;
   return ORC_OK;
 }
 
@@ -93,6 +99,41 @@ static inline long at(const grid_t* g, int i, int j, int k) {
 double orc_vanleer(double dm, double dp) {
   double s = dp * dm;
   return s > 0.0 ? (2.0 * s) / (dp + dm) : 0.0;
+}
+
+/* S2 with the compact third-order limiter LimO3 (Cada & Torrilhon 2009), one of
+ * the reconstructions of Sec. 2.3: the upper face value of a cell is
+ * q + phi(theta) dp / 2 with theta = dm / dp and
+ *   phi(theta) = max(0, min(p3, max(-theta/2, min(2 theta, p3, 1.6)))),
+ *   p3 = (2 + theta) / 3 (the unlimited third-order weight);
+ * the lower face value mirrors it, q - phi(dp / dm) dm / 2.  A zero difference
+ * leaves the face value at the cell value (the limit of phi(theta) dp as dp -> 0).
+ * The smooth-extremum switch of that paper, which needs a problem length scale,
+ * is not used: the limiter applies everywhere. */
+double orc_limo3_phi(double th) {
+  double p3 = (2.0 + th) / 3.0;
+  double inner = 2.0 * th < p3 ? 2.0 * th : p3;
+  inner = inner < 1.6 ? inner : 1.6;
+  double m = -0.5 * th > inner ? -0.5 * th : inner;
+  double r = p3 < m ? p3 : m;
+  return r > 0.0 ? r : 0.0;
+}
+
+/* upper and lower face values of cell q1 (neighbours q0 below, q2 above) */
+static double recon_hi(int recon, double q0, double q1, double q2) {
+  double dm = q1 - q0, dp = q2 - q1;
+  if (recon == ORC_LIMO3) return dp == 0.0 ? q1 : q1 + (0.5 * orc_limo3_phi(dm / dp)) * dp;
+  return q1 + 0.5 * orc_vanleer(dm, dp);
+}
+static double recon_lo(int recon, double q0, double q1, double q2) {
+  double dm = q1 - q0, dp = q2 - q1;
+  if (recon == ORC_LIMO3) return dm == 0.0 ? q1 : q1 - (0.5 * orc_limo3_phi(dp / dm)) * dm;
+  return q1 - 0.5 * orc_vanleer(dm, dp);
+}
+
+void orc_recon(int recon, double q0, double q1, double q2, double* lo, double* hi) {
+  *lo = recon_lo(recon, q0, q1, q2);
+  *hi = recon_hi(recon, q0, q1, q2);
 }
 
 /* Fast and slow magnetosonic speeds from a^2 = gamma p / rho, total and normal
@@ -186,6 +227,51 @@ static void hll(double gamma, double igm1, const double* wl, const double* wr, d
     double slr = sr * sl;
     for (int q = 0; q < 7; ++q) f[q] = ((sr * fl[q] - sl * fr[q]) + slr * (ur[q] - ul[q])) * ih;
   }
+}
+
+/* HLLC (Toro, Spruce & Speares 1994; Toro 2009 Sec. 10.4), the hydrodynamic
+ * solver the paper uses for B = 0 problems (Sec. 4.1): the magnetic field takes
+ * no part (no magnetic pressure, zero B fluxes, sound-speed bounds).  Contact
+ * speed S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R)) /
+ * (rho_L (S_L - u_L) - rho_R (S_R - u_R)); star state of side K:
+ * rho_K (S_K - u_K)/(S_K - S*) (1, S*, v1_K, v2_K, E_K/rho_K + (S* - u_K)
+ * (S* + p_K / (rho_K (S_K - u_K)))); F*_K = F_K + S_K (U*_K - U_K). */
+static void hllc(double gamma, double igm1, const double* wl0, const double* wr0, double* f,
+                 double* cmax) {
+  double wl[7], wr[7];
+  memcpy(wl, wl0, sizeof wl);
+  memcpy(wr, wr0, sizeof wr);
+  wl[4] = wl[5] = wr[4] = wr[5] = 0.0;
+  double ul[7], fl[7], ur[7], fr[7], ptl, ptr, sl, sr;
+  phys(igm1, wl, 0.0, ul, fl, &ptl);
+  phys(igm1, wr, 0.0, ur, fr, &ptr);
+  outer_speeds(gamma, wl, wr, 0.0, &sl, &sr, cmax);
+  if (sl >= 0.0) {
+    memcpy(f, fl, sizeof fl);
+    return;
+  }
+  if (sr <= 0.0) {
+    memcpy(f, fr, sizeof fr);
+    return;
+  }
+  double dl = wl[0] * (sl - wl[1]);
+  double dr = wr[0] * (sr - wr[1]);
+  double ss = ((wr[6] - wl[6]) + (dl * wl[1] - dr * wr[1])) / (dl - dr);
+  const double* w = ss >= 0.0 ? wl : wr;
+  const double* u = ss >= 0.0 ? ul : ur;
+  const double* fk = ss >= 0.0 ? fl : fr;
+  double sk = ss >= 0.0 ? sl : sr;
+  double dk = ss >= 0.0 ? dl : dr;
+  double fac = dk / (sk - ss);
+  double us[7];
+  us[0] = fac;
+  us[1] = fac * ss;
+  us[2] = fac * w[2];
+  us[3] = fac * w[3];
+  us[4] = fac * (u[4] / w[0] + (ss - w[1]) * (ss + w[6] / dk));
+  us[5] = 0.0;
+  us[6] = 0.0;
+  for (int q = 0; q < 7; ++q) f[q] = fk[q] + sk * (us[q] - u[q]);
 }
 
 /* One side's single-star state of HLLD (Miyoshi & Kusano 2005): density,
@@ -306,6 +392,8 @@ static void riemann(int solver, double gamma, double igm1, const double* wl, con
                     double bn, double* f, double* cmax) {
   if (solver == ORC_HLL)
     hll(gamma, igm1, wl, wr, bn, f, cmax);
+  else if (solver == ORC_HLLC)
+    hllc(gamma, igm1, wl, wr, f, cmax);
   else
     hlld(gamma, igm1, wl, wr, bn, f, cmax);
 }
@@ -453,10 +541,8 @@ static void faces(const grid_t* g, const orc_state* s, work_t* w, int d) {
         for (int v = 0; v < 7; ++v) {
           const double* q = w->w[frame[d][v]];
           double q0 = q[c[0]], q1 = q[c[1]], q2 = q[c[2]], q3 = q[c[3]];
-          double sl = orc_vanleer(q1 - q0, q2 - q1);
-          double sr = orc_vanleer(q2 - q1, q3 - q2);
-          wl[v] = q1 + 0.5 * sl;
-          wr[v] = q2 - 0.5 * sr;
+          wl[v] = recon_hi(g->recon, q0, q1, q2); /* upper face of cell c-1 */
+          wr[v] = recon_lo(g->recon, q1, q2, q3); /* lower face of cell c */
         }
         long o = c[2];
         riemann(g->riemann, g->gamma, g->igm1, wl, wr, bnarr[o], fl, &cmax);

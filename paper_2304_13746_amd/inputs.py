@@ -205,6 +205,24 @@ def turbulence(n: tuple | int = 256, seed: int = 2304, kpeak: float = 4.0, mach:
     return s
 
 
+def sedov(n: int = 512, r_cells: float = 3.0, energy: float = 1.0, rho0: float = 1.0,
+          p0: float = 1e-2, gamma: float = 5.0 / 3.0):
+    """Sedov-Taylor blast (Sec. 4.1 tests): periodic unit cube, rho = 1, P = 1e-2,
+    gamma = 5/3, at rest, B = 0; the cells whose centres lie within r_i =
+    r_cells cell widths of the box centre get the pressure that makes the
+    deposited energy sum(P dV)/(gamma - 1) equal ``energy`` (the ambient
+    P = 1e-2 included)."""
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h - 0.5
+    r2 = x[None, None, :] ** 2 + x[None, :, None] ** 2 + x[:, None, None] ** 2
+    inside = r2 < (r_cells * h) ** 2
+    n_in = int(np.count_nonzero(inside))
+    p_in = (gamma - 1.0) * energy / (n_in * h ** 3)
+    p = np.where(inside, p_in, p0)
+    z = np.zeros((n, n, n))
+    return assemble(rho0, z, z, z, p, z, z, z, gamma)
+
+
 def batch_boxes(nbox: int = 64, seed: int = 2304, emin: int = 16, emax: int = 128,
                 gamma: float = 5.0 / 3.0):
     """Batch of uneven periodic boxes: each edge 8 * round(e^u / 8) with

@@ -154,6 +154,30 @@ def test_hlld_without_field_is_hllc():
         assert f[i, 5] == 0.0 and f[i, 6] == 0.0
 
 
+def test_hllc_solver_is_textbook_hllc():
+    """The oracle's HLLC (the hydrodynamic solver for B = 0 problems) equals the
+    test-only textbook HLLC above, and with B = 0 agrees with HLLD to rounding;
+    any field in its input is ignored (no B flux, no magnetic pressure)."""
+    g = 5.0 / 3.0
+    w, bn = random_states(500, RNG, bfield=False)
+    wr, _ = random_states(500, RNG, bfield=False)
+    f, cm = O.riemann(O.HLLC, g, w, wr, bn)
+    fd, cmd = O.riemann(O.HLLD, g, w, wr, bn)
+    for i in range(len(bn)):
+        ref = hllc_reference(g, w[i], wr[i])
+        scale = np.max(np.abs(ref)) + 1.0
+        assert np.max(np.abs(f[i, :5] - ref)) <= 1e-13 * scale
+        assert np.max(np.abs(f[i] - fd[i])) <= 1e-12 * scale
+        assert f[i, 5] == 0.0 and f[i, 6] == 0.0
+    assert np.array_equal(cm, cmd)
+    wb, bnb = random_states(50, RNG, bfield=True)
+    fb, _ = O.riemann(O.HLLC, g, wb, wb[::-1].copy(), bnb)
+    w0 = wb.copy()
+    w0[:, 4:6] = 0.0
+    f0, _ = O.riemann(O.HLLC, g, w0, w0[::-1].copy(), np.zeros_like(bnb))
+    assert np.array_equal(fb, f0)
+
+
 @pytest.mark.parametrize("bn", [0.0, 0.8, -1.3])
 def test_hlld_stationary_contact_and_tangential_discontinuity(bn):
     """Miyoshi & Kusano (2005): HLLD resolves an isolated stationary contact

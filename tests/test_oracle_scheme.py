@@ -60,7 +60,7 @@ def test_conservation_and_divb_orszag_tang(solver):
     assert rel_err(s["rho"], s0["rho"]) > 1e-3
 
 
-@pytest.mark.parametrize("solver", SOLVERS)
+@pytest.mark.parametrize("solver", SOLVERS + [O.HLLC])
 def test_sod_converges_to_exact_solution(solver):
     """Sec. 4.1 Sod tube (gamma = 1.4, t = 0.2) on a periodic double tube of
     length 2, against the exact Euler Riemann solution; the L1 density error
