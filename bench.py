@@ -65,12 +65,13 @@ def counter_traffic(precision: str):
 
 
 def run_gpu(state, precision: str, steps: int, warmup: int, tile: int = 0, zchunk: int = 0,
-            integrator: str = "rk2", emf: str = "ec", recon: str = "plm"):
+            integrator: str = "rk2", emf: str = "ec", recon: str = "plm", n: int = N,
+            riemann: str = "hlld"):
     import torch
 
     from paper_2304_13746_amd.box import MHDBox
 
-    box = MHDBox(N, N, N, precision=precision, riemann="hlld", tile=tile, zchunk=zchunk,
+    box = MHDBox(n, n, n, precision=precision, riemann=riemann, tile=tile, zchunk=zchunk,
                  integrator=integrator, emf=emf, recon=recon)
     box.set_state(state)
     box.step(warmup)
@@ -229,7 +230,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-box batched run")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the runs of the widened scheme options (RK3, LimO3, E^0, "
-                         "arithmetic EMF)")
+                         "arithmetic EMF) and of the Sedov 512^3 hydro workload")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests in the served replay (0: skip; the full stream is 5000)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
@@ -313,6 +314,20 @@ def main():
                                          "ms_per_step": ms_step, "stage_launch_ms": ms_step / nst,
                                          "rc": r["rc"]}
                 print(f"# {name} {prec}: {ms_step:.3f} ms/cycle", file=sys.stderr, flush=True)
+        # the second workload: Sedov-Taylor blast at 512^3, B = 0 (Sec. 4.1), HLLC
+        # and HLL (the paper's choice), RK2, PLM
+        sed = I.sedov(512)
+        for riem in ("hllc", "hll"):
+            for prec in precs:
+                r = run_gpu(sed, prec, k, 1, args.tile, args.zchunk, "rk2", "ec", "plm",
+                            n=512, riemann=riem)
+                ms_step = r["ms_total"] / k
+                nxt[f"sedov512_{riem}_{prec}"] = {"value": 512 ** 3 / (ms_step * 1e-3),
+                                                  "unit": "cell-updates/s", "ms_per_step": ms_step,
+                                                  "stage_launch_ms": ms_step / 2, "rc": r["rc"]}
+                print(f"# sedov 512^3 {riem} {prec}: {ms_step:.3f} ms/cycle", file=sys.stderr,
+                      flush=True)
+        del sed
         line["next_rows"] = nxt
     if not args.no_batch:
         line["batched"] = batched_c3()

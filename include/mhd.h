@@ -52,7 +52,9 @@ extern "C" {
 #define MHD_ERR_UNSUPPORTED (-5)  /* option combination not built */
 
 typedef enum { MHD_FP64 = 0, MHD_FP32 = 1 } mhd_precision;
-typedef enum { MHD_HLLD = 0, MHD_HLL = 1 } mhd_riemann;       /* Sec. 2.3 */
+/* Riemann solvers of Sec. 2.3; HLLC is the hydrodynamic solver for B = 0
+ * problems (it ignores the field: zero B fluxes, no magnetic pressure). */
+typedef enum { MHD_HLLD = 0, MHD_HLL = 1, MHD_HLLC = 2 } mhd_riemann;
 /* Corner-EMF schemes of Sec. 2.4 (Gardiner & Stone 2005): E^c (default), E^0
  * and the arithmetic mean of the four face EMFs. */
 typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2 } mhd_emf;

@@ -3,8 +3,9 @@
 ``mhd_tune`` (libmhd) times the first-stage launch of a group of boxes, as one
 batched launch, for every stage-kernel tile and z-chunk cap, and gives every
 box the fastest shape.  This module keys that choice by the GPU, the precision,
-the solver and the multiset of box shapes, keeps it in a JSON file, and applies
-a cached choice on later calls without timing anything.  The launch shape only
+the scheme (solver, reconstruction, EMF) and the multiset of box shapes, keeps
+it in a JSON file, and applies a cached choice on later calls without timing
+anything.  The launch shape only
 changes how the work is split, never the result (FP64 is bit-identical for
 every shape), so a stale cache entry can cost time but not correctness.
 
@@ -30,10 +31,10 @@ def default_cache_path() -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "paper_2304_13746_amd", "tune.json")
 
 
-def group_key(device_name: str, precision: str, riemann: str, shapes) -> str:
-    """Cache key: device, precision, solver and the sorted (nx, ny, nz) list."""
+def group_key(device_name: str, precision: str, scheme: str, shapes) -> str:
+    """Cache key: device, precision, scheme and the sorted (nx, ny, nz) list."""
     dims = sorted(tuple(int(v) for v in s) for s in shapes)
-    return json.dumps([device_name, precision, riemann, dims], separators=(",", ":"))
+    return json.dumps([device_name, precision, scheme, dims], separators=(",", ":"))
 
 
 class Tuner:
@@ -70,8 +71,9 @@ class Tuner:
 
     def key(self, boxes) -> str:
         b0 = boxes[0]
-        riemann = "hll" if b0.params.riemann == L.MHD_HLL else "hlld"
-        return group_key(self._device_name(b0), b0.precision, riemann,
+        pr = b0.params
+        scheme = f"riemann{pr.riemann}/recon{pr.recon}/emf{pr.emf}"
+        return group_key(self._device_name(b0), b0.precision, scheme,
                          [(b.shape[2], b.shape[1], b.shape[0]) for b in boxes])
 
     def lookup(self, boxes):

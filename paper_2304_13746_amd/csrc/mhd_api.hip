@@ -408,7 +408,8 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
       !(p->cfl < 1.0))
     return MHD_ERR_INVALID_ARG;
   if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return MHD_ERR_INVALID_ARG;
-  if (p->riemann != MHD_HLLD && p->riemann != MHD_HLL) return MHD_ERR_INVALID_ARG;
+  if (p->riemann != MHD_HLLD && p->riemann != MHD_HLL && p->riemann != MHD_HLLC)
+    return MHD_ERR_INVALID_ARG;
   if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH)
     return MHD_ERR_UNSUPPORTED;
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3) return MHD_ERR_UNSUPPORTED;

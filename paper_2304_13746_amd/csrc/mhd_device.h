@@ -316,11 +316,53 @@ __device__ __forceinline__ void flux_hlld(R gamma, R igm1, const Prim<R>& l, con
   }
 }
 
+// HLLC (Toro, Spruce & Speares 1994) for B = 0 problems: the field takes no
+// part (zero B fluxes, no magnetic pressure, sound-speed bounds).  Contact speed
+// S* = (p_R - p_L + d_L u_L - d_R u_R) / (d_L - d_R), d_K = rho_K (S_K - u_K);
+// star state d_K/(S_K - S*) (1, S*, v1, v2, E/rho + (S* - u)(S* + p/d_K)).
+template <typename R>
+__device__ __forceinline__ void flux_hllc(R gamma, R igm1, Prim<R> l, Prim<R> r, R* f, R& cmax) {
+  l.b1 = l.b2 = r.b1 = r.b2 = R(0);
+  R sl, sr;
+  outer_speeds(gamma, l, r, R(0), sl, sr, cmax);
+  if (sl >= R(0) || sr <= R(0)) {  // supersonic: upwind physical flux
+    Cons<R> c;
+    physical(sl >= R(0) ? l : r, R(0), igm1, c);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q] = c.f[q];
+    return;
+  }
+  const R dl = l.rho * (sl - l.un);
+  const R dr = r.rho * (sr - r.un);
+  const R ss = dvd((r.p - l.p) + (dl * l.un - dr * r.un), dl - dr);
+  const bool left = ss >= R(0);
+  const Prim<R> w = pick(left, l, r);
+  const R sk = left ? sl : sr;
+  const R dk = left ? dl : dr;
+  Cons<R> c;
+  physical(w, R(0), igm1, c);
+  const R fac = dvd(dk, sk - ss);
+  R us[7];
+  us[0] = fac;
+  us[1] = fac * ss;
+  us[2] = fac * w.v1;
+  us[3] = fac * w.v2;
+  us[4] = fac * (dvd(c.u[4], w.rho) + (ss - w.un) * (ss + dvd(w.p, dk)));
+  us[5] = R(0);
+  us[6] = R(0);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) f[q] = c.f[q] + sk * (us[q] - c.u[q]);
+}
+
+enum { SOLVER_HLLD = 0, SOLVER_HLL = 1, SOLVER_HLLC = 2 };
+
 template <int SOLVER, typename R>
 __device__ __forceinline__ void riemann(R gamma, R igm1, const Prim<R>& l, const Prim<R>& r, R bn,
                                         R* f, R& cmax) {
-  if constexpr (SOLVER == 1)
+  if constexpr (SOLVER == SOLVER_HLL)
     flux_hll(gamma, igm1, l, r, bn, f, cmax);
+  else if constexpr (SOLVER == SOLVER_HLLC)
+    flux_hllc(gamma, igm1, l, r, f, cmax);
   else
     flux_hlld(gamma, igm1, l, r, bn, f, cmax);
 }

@@ -700,11 +700,16 @@ static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) 
 template <typename R, int TX, int TY>
 static hipError_t launch_tile(const BatchArgs& ba, int solver, int recon, hipStream_t st,
                               bool prepare) {
-  if (solver == 0)
-    return recon == RECON_LIMO3 ? launch_emf<R, 0, RECON_LIMO3, TX, TY>(ba, st, prepare)
-                                : launch_emf<R, 0, RECON_PLM, TX, TY>(ba, st, prepare);
-  return recon == RECON_LIMO3 ? launch_emf<R, 1, RECON_LIMO3, TX, TY>(ba, st, prepare)
-                              : launch_emf<R, 1, RECON_PLM, TX, TY>(ba, st, prepare);
+  const bool lim = recon == RECON_LIMO3;
+  if (solver == SOLVER_HLLD)
+    return lim ? launch_emf<R, SOLVER_HLLD, RECON_LIMO3, TX, TY>(ba, st, prepare)
+               : launch_emf<R, SOLVER_HLLD, RECON_PLM, TX, TY>(ba, st, prepare);
+  if (solver == SOLVER_HLL)
+    return lim ? launch_emf<R, SOLVER_HLL, RECON_LIMO3, TX, TY>(ba, st, prepare)
+               : launch_emf<R, SOLVER_HLL, RECON_PLM, TX, TY>(ba, st, prepare);
+  // HLLC (B = 0 problems): the EMFs vanish, so only the default scheme is built
+  return lim ? launch_mode<R, SOLVER_HLLC, RECON_LIMO3, EMF_EC, TX, TY>(ba, st, prepare)
+             : launch_mode<R, SOLVER_HLLC, RECON_PLM, EMF_EC, TX, TY>(ba, st, prepare);
 }
 
 // Raise the LDS limit of every mode of one (solver, reconstruction, EMF) choice.

@@ -30,7 +30,7 @@ def oracle_params(dims, l=(1.0, 1.0, 1.0), riemann="hlld", integrator="rk2", gam
                   cfl=0.3, emf="ec", recon="plm"):
     nx, ny, nz = dims
     return O.Params(nx, ny, nz, *l, gamma=gamma, cfl=cfl,
-                    riemann={"hlld": O.HLLD, "hll": O.HLL}[riemann],
+                    riemann={"hlld": O.HLLD, "hll": O.HLL, "hllc": O.HLLC}[riemann],
                     integrator={"rk2": O.RK2, "euler": O.EULER, "rk3": O.RK3}[integrator],
                     emf={"ec": O.EMF_EC, "e0": O.EMF_E0, "arith": O.EMF_ARITH}[emf],
                     recon={"plm": O.PLM, "limo3": O.LIMO3}[recon])

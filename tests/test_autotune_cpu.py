@@ -13,7 +13,8 @@ class FakeBox:
     def __init__(self, nx, ny, nz, precision="fp32"):
         self.shape = (nz, ny, nx)
         self.precision = precision
-        self.params = types.SimpleNamespace(riemann=L.MHD_HLLD)
+        self.params = types.SimpleNamespace(riemann=L.MHD_HLLD, recon=L.MHD_PLM,
+                                            emf=L.MHD_EMF_EC)
         self.launch = None
 
     def set_launch(self, tile, zchunk):

@@ -184,3 +184,27 @@ def test_limo3_fp32_within_tolerance():
     err = max_rel(g, o)
     print("limo3 fp32 max rel", err)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "hll"])
+def test_sedov_hydro_fp64_bit_exact(riemann):
+    """The hydrodynamic workload (Sedov-Taylor blast, B = 0, Sec. 4.1) with HLLC
+    or HLL on a 40^3 box, 6 cycles: bit-identical to the oracle; the field
+    stays exactly zero."""
+    need_gpu()
+    n = 40
+    s = I.sedov(n)
+    g, o, gd, od, (tg, to) = run_both(s, (n, n, n), 6, riemann=riemann, per_step=True)
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+    for f in ("bx", "by", "bz"):
+        assert not g[f].any()
+
+
+def test_sedov_hllc_fp32_within_tolerance():
+    need_gpu()
+    s = I.to_float32_exact(I.sedov(32))
+    g, o, _, _, _ = run_both(s, (32, 32, 32), 5, riemann="hllc", precision="fp32")
+    err = max_rel(g, o)  # the field group is exactly zero on both sides
+    print("sedov hllc fp32 max rel", err)
+    assert err <= 1e-5
