@@ -56,6 +56,11 @@ class _State(C.Structure):
     _fields_ = [(f, C.POINTER(C.c_double)) for f in FIELDS]
 
 
+class _Vpot(C.Structure):
+    _fields_ = [("ax", C.POINTER(C.c_double)), ("ay", C.POINTER(C.c_double)),
+                ("az", C.POINTER(C.c_double)), ("b0", C.c_double * 3)]
+
+
 _lib = None
 
 
@@ -73,6 +78,8 @@ def lib():
         L.orc_step.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, C.c_int, C.c_double]
         L.orc_diagnostics.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp]
         L.orc_mass_flux.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, dp]
+        L.orc_step_vp.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.POINTER(_Vpot), dp, dp,
+                                  C.c_int, C.c_double]
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
         L.orc_vanleer.restype = C.c_double
         L.orc_limo3_phi.argtypes = [C.c_double]
@@ -135,6 +142,22 @@ def max_invdt(p: Params, s: dict) -> float:
     if rc not in (OK,):
         raise RuntimeError(f"orc_max_invdt failed: {rc}")
     return out.value
+
+
+def step_vp(p: Params, s: dict, a: dict, t: float, dt_next: float, nsteps: int,
+            t_stop: float = 0.0, check: bool = True):
+    """orc_step with the field carried by the edge potential a = {"ax", "ay",
+    "az", "b0"}: advances s and a in place (s's face field becomes b0 + curl A)."""
+    for k in ("ax", "ay", "az"):
+        assert a[k].dtype == np.float64 and a[k].flags.c_contiguous and a[k].shape == s["rho"].shape
+    v = _Vpot(_dptr(a["ax"]), _dptr(a["ay"]), _dptr(a["az"]), (C.c_double * 3)(*a["b0"]))
+    tt = C.c_double(t)
+    dd = C.c_double(dt_next)
+    rc = lib().orc_step_vp(C.byref(p.c()), C.byref(_cstate(p, s)), C.byref(v), C.byref(tt),
+                           C.byref(dd), int(nsteps), float(t_stop))
+    if check and rc != OK:
+        raise RuntimeError(f"orc_step_vp failed: {rc}")
+    return tt.value, dd.value, rc
 
 
 def mass_flux(p: Params, s: dict):

@@ -613,8 +613,13 @@ static void emfs(const grid_t* g, work_t* w) {
  * dst; if base is given, dst = ws S_dt(src) + w0 base (later stages of a
  * Runge-Kutta cycle, Sec. 2.7; base and dst may be the same arrays).  If maxinv
  * is given it receives the CFL maximum of eq. (cfl) measured on src. */
+static void vp_update(const grid_t* g, const work_t* w, const orc_vpot* asrc,
+                      const orc_vpot* abase, double ws, double w0, orc_vpot* adst, double dt);
+static void curl_b(const grid_t* g, const orc_vpot* a, orc_state* s);
+
 static int stage(const grid_t* g, const orc_state* src, const orc_state* base, double ws,
-                 double w0, orc_state* dst, double dt, double* maxinv, work_t* w) {
+                 double w0, orc_state* dst, double dt, double* maxinv, work_t* w,
+                 const orc_vpot* asrc, const orc_vpot* abase, orc_vpot* adst) {
   int bad = prim_all(g, src, w);
   for (int d = 0; d < 3; ++d) faces(g, src, w, d);
   emfs(g, w);
@@ -673,7 +678,52 @@ static int stage(const grid_t* g, const orc_state* src, const orc_state* base, d
     }
   }
   if (maxinv) *maxinv = mx;
+  if (adst) {
+    /* vector-potential form (eq. ind_vec): A* = A - dt E on every edge, combined
+     * like U, and the face field taken as B0 + curl A instead of the Stokes update */
+    vp_update(g, w, asrc, abase, ws, w0, adst, dt);
+    curl_b(g, adst, dst);
+  }
   return bad;
+}
+
+static void vp_update(const grid_t* g, const work_t* w, const orc_vpot* asrc,
+                      const orc_vpot* abase, double ws, double w0, orc_vpot* adst, double dt) {
+  const double* as[3] = {asrc->ax, asrc->ay, asrc->az};
+  const double* ab[3] = {abase ? abase->ax : 0, abase ? abase->ay : 0, abase ? abase->az : 0};
+  double* ad[3] = {adst->ax, adst->ay, adst->az};
+  for (int d = 0; d < 3; ++d) {
+    const double* e = w->ed[d];
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < g->n; ++c) {
+      double a = as[d][c] - dt * e[c];
+      ad[d][c] = abase ? ws * a + w0 * ab[d][c] : a;
+    }
+  }
+  for (int d = 0; d < 3; ++d) adst->b0[d] = asrc->b0[d];
+}
+
+/* Face field from the edge vector potential: B = B0 + curl A by Stokes' theorem
+ * on each face (B0 the uniform mean field a periodic potential cannot carry). */
+static void curl_b(const grid_t* g, const orc_vpot* a, orc_state* s) {
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < g->nz; ++k) {
+    int kp = up(k, g->nz);
+    for (int j = 0; j < g->ny; ++j) {
+      int jp = up(j, g->ny);
+      for (int i = 0; i < g->nx; ++i) {
+        int ip = up(i, g->nx);
+        long c = at(g, i, j, k);
+        long cxp = at(g, ip, j, k), cyp = at(g, i, jp, k), czp = at(g, i, j, kp);
+        s->bx[c] = a->b0[0] + ((a->az[cyp] - a->az[c]) * g->idl[1] -
+                               (a->ay[czp] - a->ay[c]) * g->idl[2]);
+        s->by[c] = a->b0[1] + ((a->ax[czp] - a->ax[c]) * g->idl[2] -
+                               (a->az[cxp] - a->az[c]) * g->idl[0]);
+        s->bz[c] = a->b0[2] + ((a->ay[cxp] - a->ay[c]) * g->idl[0] -
+                               (a->ax[cyp] - a->ax[c]) * g->idl[1]);
+      }
+    }
+  }
 }
 
 /* ---------------------------------------------------------------- public */
@@ -754,13 +804,23 @@ static double clip_dt(double dt, double t, double t_stop) {
   return dt;
 }
 
-int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int nsteps,
-             double t_stop) {
+static int vpot_alloc(orc_vpot* a, long n, double** block) {
+  *block = (double*)malloc(sizeof(double) * 3 * n);
+  if (!*block) return ORC_ERR_NOMEM;
+  a->ax = *block;
+  a->ay = *block + n;
+  a->az = *block + 2 * n;
+  return ORC_OK;
+}
+
+static int step_impl(const orc_params* p, orc_state* s, orc_vpot* a, double* t, double* dt_next,
+                     int nsteps, double t_stop) {
   int rc = check_params(p);
   if (rc) return rc;
   if (!s || !t || !dt_next || nsteps < 0) return ORC_ERR_INVALID_ARG;
   grid_t g;
   grid_init(&g, p);
+  if (a) curl_b(&g, a, s); /* the face field of the vector-potential form */
   if (!(*dt_next > 0.0)) {
     double mi;
     rc = orc_max_invdt(p, s, &mi);
@@ -769,31 +829,30 @@ int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int 
   }
   work_t w;
   orc_state tmp, tmp2;
-  double *tblock, *tblock2 = NULL;
+  orc_vpot at1, at2;
+  double *tblock = NULL, *tblock2 = NULL, *ablock = NULL, *ablock2 = NULL;
+  const int rk3 = p->integrator == ORC_RK3;
   if (work_alloc(&w, g.n)) return ORC_ERR_NOMEM;
-  if (state_alloc(&tmp, g.n, &tblock)) {
-    free(w.block);
-    return ORC_ERR_NOMEM;
-  }
-  if (p->integrator == ORC_RK3 && state_alloc(&tmp2, g.n, &tblock2)) {
-    free(w.block);
-    free(tblock);
-    return ORC_ERR_NOMEM;
-  }
+  rc = state_alloc(&tmp, g.n, &tblock);
+  if (!rc && rk3) rc = state_alloc(&tmp2, g.n, &tblock2);
+  if (!rc && a) rc = vpot_alloc(&at1, g.n, &ablock);
+  if (!rc && a && rk3) rc = vpot_alloc(&at2, g.n, &ablock2);
   int bad = 0;
-  for (int n = 0; n < nsteps; ++n) {
+  for (int n = 0; n < nsteps && !rc; ++n) {
     double dt = clip_dt(*dt_next, *t, t_stop);
     double mi = 0.0;
+    orc_vpot* a1 = a ? &at1 : NULL;
+    orc_vpot* a2 = a ? &at2 : NULL;
     /* stage 1: U_1 = S_dt(U_0)  (w_1 = 1, w0_1 = 0) */
-    bad |= stage(&g, s, NULL, 1.0, 0.0, &tmp, dt, &mi, &w);
+    bad |= stage(&g, s, NULL, 1.0, 0.0, &tmp, dt, &mi, &w, a, NULL, a1);
     if (p->integrator == ORC_RK2) {
       /* stage 2: U^{n+1} = 1/2 S_dt(U_1) + 1/2 U_0 */
-      bad |= stage(&g, &tmp, s, 0.5, 0.5, s, dt, NULL, &w);
-    } else if (p->integrator == ORC_RK3) {
+      bad |= stage(&g, &tmp, s, 0.5, 0.5, s, dt, NULL, &w, a1, a, a);
+    } else if (rk3) {
       /* stage 2: U_2 = 1/4 S_dt(U_1) + 3/4 U_0; stage 3: U^{n+1} = 2/3 S_dt(U_2)
        * + 1/3 U_0 */
-      bad |= stage(&g, &tmp, s, 0.25, 0.75, &tmp2, dt, NULL, &w);
-      bad |= stage(&g, &tmp2, s, 2.0 / 3.0, 1.0 / 3.0, s, dt, NULL, &w);
+      bad |= stage(&g, &tmp, s, 0.25, 0.75, &tmp2, dt, NULL, &w, a1, a, a2);
+      bad |= stage(&g, &tmp2, s, 2.0 / 3.0, 1.0 / 3.0, s, dt, NULL, &w, a2, a, a);
     } else {
       memcpy(s->rho, tmp.rho, sizeof(double) * g.n);
       memcpy(s->mx, tmp.mx, sizeof(double) * g.n);
@@ -803,6 +862,11 @@ int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int 
       memcpy(s->bx, tmp.bx, sizeof(double) * g.n);
       memcpy(s->by, tmp.by, sizeof(double) * g.n);
       memcpy(s->bz, tmp.bz, sizeof(double) * g.n);
+      if (a) {
+        memcpy(a->ax, at1.ax, sizeof(double) * g.n);
+        memcpy(a->ay, at1.ay, sizeof(double) * g.n);
+        memcpy(a->az, at1.az, sizeof(double) * g.n);
+      }
     }
     *t += dt;
     *dt_next = p->cfl / mi;
@@ -810,7 +874,21 @@ int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int 
   free(w.block);
   free(tblock);
   free(tblock2);
+  free(ablock);
+  free(ablock2);
+  if (rc) return rc;
   return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next, int nsteps,
+             double t_stop) {
+  return step_impl(p, s, NULL, t, dt_next, nsteps, t_stop);
+}
+
+int orc_step_vp(const orc_params* p, orc_state* s, orc_vpot* a, double* t, double* dt_next,
+                int nsteps, double t_stop) {
+  if (!a || !a->ax || !a->ay || !a->az) return ORC_ERR_INVALID_ARG;
+  return step_impl(p, s, a, t, dt_next, nsteps, t_stop);
 }
 
 /* Neumaier-compensated running sum. */

@@ -52,6 +52,21 @@ typedef struct {
 /* Max over the volume of sum_d c_max,d / dl_d (eq. cfl) for the given state. */
 int orc_max_invdt(const orc_params* p, const orc_state* s, double* out);
 
+/* Vector-potential form of constrained transport (Sec. 2.4, eq. ind_vec): the
+ * edge potential A (ax on (i, j-1/2, k-1/2), ay on (i-1/2, j, k-1/2), az on
+ * (i-1/2, j-1/2, k), arrays of n cells like the state) evolves by dA/dt = -E
+ * and the face field is B = b0 + curl A, b0 the uniform mean field. */
+typedef struct {
+  double *ax, *ay, *az;
+  double b0[3];
+} orc_vpot;
+
+/* orc_step with the field carried by A: on entry the face field of s is set to
+ * b0 + curl A; every stage updates A with the corner EMFs (combined with the
+ * stage weights like U) and re-derives the face field from it. */
+int orc_step_vp(const orc_params* p, orc_state* s, orc_vpot* a, double* t, double* dt_next,
+                int nsteps, double t_stop);
+
 /* Mass flux F_rho of the Riemann solve (S3) on every face of the state: fx[c] on
  * the x-face at (i-1/2, j, k) of cell c, fy and fz likewise (arrays of n cells). */
 int orc_mass_flux(const orc_params* p, const orc_state* s, double* fx, double* fy, double* fz);

@@ -87,7 +87,7 @@ int main(int argc, char** argv) {
   work_alloc(&w, g.n);
   CD mi;
   g_add = g_mul = g_div = g_sqrt = 0;
-  stage(&g, &s, nullptr, CD(1), CD(0), &d, CD(1e-4), &mi, &w);
+  stage(&g, &s, nullptr, CD(1), CD(0), &d, CD(1e-4), &mi, &w, nullptr, nullptr, nullptr);
   real_t c = (real_t)n;
   std::printf("{\"cells\": %ld, \"add_sub\": %.2f, \"mul\": %.2f, \"div\": %.2f, \"sqrt\": %.2f, "
               "\"flops\": %.2f}\n", n, g_add / c, g_mul / c, g_div / c, g_sqrt / c,

@@ -78,12 +78,14 @@ def to_float32_exact(s: dict) -> dict:
 
 # ------------------------------------------------------------ Orszag-Tang
 
-def orszag_tang(n: int = 32, seed: int = 2304, gamma: float = 5.0 / 3.0, noise: float = 1e-3):
+def orszag_tang(n: int = 32, seed: int = 2304, gamma: float = 5.0 / 3.0, noise: float = 1e-3,
+                potential: bool = False):
     """Orszag-Tang vortex (Sec. 4.2) on the periodic unit cube, extruded in z.
 
     rho = 25/(36 pi) (1 + noise u), u ~ U(-1, 1) seeded; p = 5/(12 pi);
     v = (-sin 2 pi y, sin 2 pi x, 0); B = B0 (-sin 2 pi y, sin 4 pi x, 0) with
     B0 = 1/sqrt(4 pi), from A_z = B0 [cos(4 pi x)/(4 pi) + cos(2 pi y)/(2 pi)].
+    With ``potential`` also returns the edge potential {"ax", "ay", "az", "b0"}.
     """
     nx = ny = nz = n
     dl = (1.0 / nx, 1.0 / ny, 1.0 / nz)
@@ -102,10 +104,13 @@ def orszag_tang(n: int = 32, seed: int = 2304, gamma: float = 5.0 / 3.0, noise: 
     az = np.broadcast_to(az, (nz, ny, nx)).copy()
     zero = np.zeros((nz, ny, nx))
     bx, by, bz = face_b_from_potential(zero, zero, az, dl)
-    return assemble(rho, vx, vy, vz, p, bx, by, bz, gamma)
+    st = assemble(rho, vx, vy, vz, p, bx, by, bz, gamma)
+    if potential:
+        return st, {"ax": zero.copy(), "ay": zero.copy(), "az": az, "b0": (0.0, 0.0, 0.0)}
+    return st
 
 
-def orszag_tang_3d(n: int = 256, gamma: float = 5.0 / 3.0):
+def orszag_tang_3d(n: int = 256, gamma: float = 5.0 / 3.0, potential: bool = False):
     """Three-dimensional Orszag-Tang performance problem (Sec. 5).
 
     v = (-sin 2 pi y, sin 2 pi x + cos 2 pi z, cos 2 pi x),
@@ -131,7 +136,17 @@ def orszag_tang_3d(n: int = 256, gamma: float = 5.0 / 3.0):
     ay = np.broadcast_to(b0 * np.sin(tp * xf) / tp, shape).copy()
     az = np.broadcast_to(b0 * (np.cos(2 * tp * xf) / (2 * tp) + np.cos(tp * yf) / tp), shape).copy()
     bx, by, bz = face_b_from_potential(ax, ay, az, dl)
-    return assemble(rho, vx, vy, vz, p, bx, by, bz, gamma)
+    st = assemble(rho, vx, vy, vz, p, bx, by, bz, gamma)
+    if potential:
+        return st, {"ax": ax, "ay": ay, "az": az, "b0": (0.0, 0.0, 0.0)}
+    return st
+
+
+def uniform_field_potential(shape, b0):
+    """Edge potential of a uniform field on a periodic box: A = 0 and the mean
+    field b0 carried separately (a periodic potential has no mean curl)."""
+    z = np.zeros(shape)
+    return {"ax": z, "ay": z.copy(), "az": z.copy(), "b0": tuple(float(v) for v in b0)}
 
 
 # ----------------------------------------------------------- turbulence
