@@ -66,13 +66,16 @@ def counter_traffic(precision: str):
 
 def run_gpu(state, precision: str, steps: int, warmup: int, tile: int = 0, zchunk: int = 0,
             integrator: str = "rk2", emf: str = "ec", recon: str = "plm", n: int = N,
-            riemann: str = "hlld"):
+            riemann: str = "hlld", potential=None):
     import torch
 
     from paper_2304_13746_amd.box import MHDBox
 
+    ct, b0 = ("vecpot", potential["b0"]) if potential else ("face", (0.0, 0.0, 0.0))
     box = MHDBox(n, n, n, precision=precision, riemann=riemann, tile=tile, zchunk=zchunk,
-                 integrator=integrator, emf=emf, recon=recon)
+                 integrator=integrator, emf=emf, recon=recon, ct=ct, b0=b0)
+    if potential:
+        state = dict(state, ax=potential["ax"], ay=potential["ay"], az=potential["az"])
     box.set_state(state)
     box.step(warmup)
     torch.cuda.synchronize()
@@ -230,7 +233,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-box batched run")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the runs of the widened scheme options (RK3, LimO3, E^0, "
-                         "arithmetic EMF) and of the Sedov 512^3 hydro workload")
+                         "arithmetic EMF, vector-potential CT) and of the Sedov 512^3 hydro "
+                         "workload")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests in the served replay (0: skip; the full stream is 5000)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
@@ -314,6 +318,15 @@ def main():
                                          "ms_per_step": ms_step, "stage_launch_ms": ms_step / nst,
                                          "rc": r["rc"]}
                 print(f"# {name} {prec}: {ms_step:.3f} ms/cycle", file=sys.stderr, flush=True)
+        # the vector-potential form of constrained transport (FP64): the same
+        # input with B = (0.2, 0, 0) carried as the mean field and A = 0
+        pot = I.uniform_field_potential(state["rho"].shape, (0.2, 0.0, 0.0))
+        r = run_gpu(state, "fp64", k, 1, args.tile, args.zchunk, potential=pot)
+        ms_step = r["ms_total"] / k
+        nxt["ct_vecpot_fp64"] = {"value": N ** 3 / (ms_step * 1e-3), "unit": "cell-updates/s",
+                                 "ms_per_step": ms_step, "rc": r["rc"]}
+        print(f"# vector-potential CT fp64: {ms_step:.3f} ms/cycle", file=sys.stderr, flush=True)
+        del pot
         # the second workload: Sedov-Taylor blast at 512^3, B = 0 (Sec. 4.1), HLLC
         # and HLL (the paper's choice), RK2, PLM
         sed = I.sedov(512)

@@ -61,6 +61,11 @@ typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2 } mhd_emf;
 /* Reconstructions of Sec. 2.3: van Leer PLM (default) and the compact
  * third-order LimO3 limiter (Cada & Torrilhon 2009), both on the primitives. */
 typedef enum { MHD_PLM = 0, MHD_LIMO3 = 1 } mhd_recon;
+/* Constrained transport (Sec. 2.4): the face field updated by the discrete
+ * Stokes theorem, or carried by an edge vector potential A (eqs. ind_vec:
+ * dA/dt = -E, B = b0 + curl A, b0 the uniform mean field); the potential form
+ * is built for FP64 with the E^c scheme and HLLD/HLL. */
+typedef enum { MHD_CT_FACE = 0, MHD_CT_VECPOT = 1 } mhd_ct;
 typedef enum { MHD_RK2 = 0, MHD_EULER = 1, MHD_RK3 = 2 } mhd_integrator; /* Tab. weights */
 
 typedef struct mhd_ctx mhd_ctx; /* opaque */
@@ -84,11 +89,18 @@ typedef struct {
   int tile;               /* MHD_TILE_*, 0 = default (24x8) */
   int zchunk;             /* z-planes per thread block, 0 = automatic */
   int recon;              /* mhd_recon */
+  int ct;                 /* mhd_ct */
+  double b0[3];           /* mean field of MHD_CT_VECPOT (ignored otherwise) */
 } mhd_params;
 
 typedef struct {
   void *rho, *mx, *my, *mz, *en; /* cell-centred, device pointers */
   void *bx, *by, *bz;            /* face-centred, device pointers */
+  /* edge potential of MHD_CT_VECPOT: ax[k][j][i] on (i, j-1/2, k-1/2), ay on
+   * (i-1/2, j, k-1/2), az on (i-1/2, j-1/2, k); NULL otherwise.  With the
+   * potential form set_state takes A (the face field is derived as b0 + curl A,
+   * bx/by/bz may be NULL) and get_state also returns A when these are set. */
+  void *ax, *ay, *az;
 } mhd_state_view;
 
 typedef struct {
@@ -101,10 +113,10 @@ typedef struct {
   unsigned status; /* latched device status bits (0 = fine) */
 } mhd_diag;
 
-/* Device bytes a context with these parameters needs (only the grid, precision
- * and integrator fields are read): two state buffers of 8 fields, three for
- * MHD_RK3, plus under 1 MB of scalars and partial sums.  Returns 0 if the grid
- * is invalid. */
+/* Device bytes a context with these parameters needs (only the grid, precision,
+ * integrator and ct fields are read): two state buffers of 8 fields (11 with
+ * MHD_CT_VECPOT), three buffers for MHD_RK3, plus under 1 MB of scalars and
+ * partial sums.  Returns 0 if the grid is invalid. */
 size_t mhd_workspace_bytes(const mhd_params* params);
 
 /* Validate params and build a context on the borrowed workspace.  *out receives

@@ -23,6 +23,7 @@ MHD_FP64, MHD_FP32 = 0, 1
 MHD_HLLD, MHD_HLL, MHD_HLLC = 0, 1, 2
 MHD_EMF_EC, MHD_EMF_E0, MHD_EMF_ARITH = 0, 1, 2
 MHD_PLM, MHD_LIMO3 = 0, 1
+MHD_CT_FACE, MHD_CT_VECPOT = 0, 1
 MHD_RK2, MHD_EULER, MHD_RK3 = 0, 1, 2
 TILE_16x16, TILE_24x8 = 1, 2
 
@@ -39,11 +40,12 @@ class Params(C.Structure):
                 ("integrator", C.c_int),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stream", C.c_void_p), ("tile", C.c_int), ("zchunk", C.c_int),
-                ("recon", C.c_int)]
+                ("recon", C.c_int), ("ct", C.c_int), ("b0", C.c_double * 3)]
 
 
 class StateView(C.Structure):
-    _fields_ = [(f, C.c_void_p) for f in ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")]
+    _fields_ = [(f, C.c_void_p) for f in ("rho", "mx", "my", "mz", "en", "bx", "by", "bz",
+                                           "ax", "ay", "az")]
 
 
 class Diag(C.Structure):

@@ -24,13 +24,18 @@ RECON = {"plm": L.MHD_PLM, "limo3": L.MHD_LIMO3}
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
 
 
+POTENTIAL = ("ax", "ay", "az")
+CT = {"face": L.MHD_CT_FACE, "vecpot": L.MHD_CT_VECPOT}
+
+
 def _view(tensors: dict) -> L.StateView:
-    return L.StateView(*[tensors[f].data_ptr() for f in FIELDS])
+    return L.StateView(*[tensors[f].data_ptr() if f in tensors else None
+                         for f in FIELDS + POTENTIAL])
 
 
 def make_params(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, gamma=5.0 / 3.0, cfl=0.3, precision="fp64",
                 riemann="hlld", integrator="rk2", tile=0, zchunk=0, emf="ec",
-                recon="plm") -> L.Params:
+                recon="plm", ct="face", b0=(0.0, 0.0, 0.0)) -> L.Params:
     p = L.Params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.lx, p.ly, p.lz = float(lx), float(ly), float(lz)
@@ -39,13 +44,15 @@ def make_params(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, gamma=5.0 / 3.0, cfl=0.3, pr
     p.riemann = RIEMANN[riemann]
     p.emf = EMF[emf]
     p.recon = RECON[recon]
+    p.ct = CT[ct]
+    p.b0 = (C.c_double * 3)(*[float(v) for v in b0])
     p.integrator = INTEGRATOR[integrator]
     p.tile, p.zchunk = int(tile), int(zchunk)
     return p
 
 
-def workspace_bytes(nx, ny, nz, precision="fp64", tile=0, integrator="rk2") -> int:
-    p = make_params(nx, ny, nz, precision=precision, tile=tile, integrator=integrator)
+def workspace_bytes(nx, ny, nz, precision="fp64", tile=0, integrator="rk2", ct="face") -> int:
+    p = make_params(nx, ny, nz, precision=precision, tile=tile, integrator=integrator, ct=ct)
     return int(L.lib().mhd_workspace_bytes(C.byref(p)))
 
 
@@ -55,7 +62,7 @@ class MHDBox:
     def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, gamma=5.0 / 3.0, cfl=0.3,
                  precision="fp64", riemann="hlld", integrator="rk2", device="cuda:0",
                  stream: torch.cuda.Stream | None = None, tile=0, zchunk=0, emf="ec",
-                 recon="plm"):
+                 recon="plm", ct="face", b0=(0.0, 0.0, 0.0)):
         self.lib = L.lib()
         self.device = torch.device(device)
         self.precision = precision
@@ -64,8 +71,9 @@ class MHDBox:
         # an explicit stream (default priority): torch's default stream may be a
         # per-thread stream that the HIP null stream does not order against
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.vecpot = ct == "vecpot"
         p = make_params(nx, ny, nz, lx, ly, lz, gamma, cfl, precision, riemann, integrator, tile,
-                        zchunk, emf, recon)
+                        zchunk, emf, recon, ct, b0)
         nbytes = int(self.lib.mhd_workspace_bytes(C.byref(p)))
         if nbytes == 0:
             raise L.MHDError(L.MHD_ERR_INVALID_ARG, "mhd_workspace_bytes")
@@ -81,9 +89,14 @@ class MHDBox:
 
     # ---- state in / out
 
+    def _fields(self):
+        return FIELDS + POTENTIAL if self.vecpot else FIELDS
+
     def _to_device(self, state: dict) -> dict:
         out = {}
-        for f in FIELDS:
+        for f in self._fields():
+            if self.vecpot and f in ("bx", "by", "bz") and f not in state:
+                continue  # derived from the potential
             a = state[f]
             if isinstance(a, np.ndarray):
                 a = torch.from_numpy(np.ascontiguousarray(a))
@@ -113,7 +126,7 @@ class MHDBox:
         """Copy the state out (synchronises the box's stream)."""
         with torch.cuda.stream(self.stream):
             out = {f: torch.empty(self.shape, dtype=self.dtype, device=self.device)
-                   for f in FIELDS}
+                   for f in self._fields()}
         t = C.c_double()
         dt = C.c_double()
         v = _view(out)
@@ -125,7 +138,7 @@ class MHDBox:
 
     def get_state_numpy(self, check: bool = True):
         s, t, dt, rc = self.get_state(check)
-        return {f: s[f].double().cpu().numpy() for f in FIELDS}, t, dt, rc
+        return {f: s[f].double().cpu().numpy() for f in s}, t, dt, rc
 
     def diagnostics(self) -> dict:
         d = L.Diag()

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmhd.so")
-SOURCES = ["mhd_api.hip", "mhd_stage_f64.hip", "mhd_stage_f32.hip"]
+SOURCES = ["mhd_api.hip", "mhd_stage_f64.hip", "mhd_stage_f32.hip", "mhd_vpot.hip"]
 ARCH = os.environ.get("MHD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",

@@ -18,8 +18,9 @@ struct mhd_ctx {
   long long ncell;
   double idl[3];     // 1 / (l_d / n_d)
   double dv;         // cell volume
-  void* buf[kMaxBuf][8];  // state buffers of 8 fields (3 for RK3, else 2)
+  void* buf[kMaxBuf][kFields];  // state buffers (3 for RK3, else 2)
   int nbuf;
+  int nfield;  // fields per buffer: 8, or 11 with the vector-potential form
   int cur;           // buffer holding the state
   Scalars* sc;       // device scalars
   BoxDesc* desc;     // device copy of this box's descriptor
@@ -52,6 +53,7 @@ size_t field_bytes(const mhd_params* p) {
 
 // state buffers a context needs: U_0 and one per intermediate stage result
 int nbuf_of(const mhd_params* p) { return p->integrator == MHD_RK3 ? 3 : 2; }
+int nfield_of(const mhd_params* p) { return p->ct == MHD_CT_VECPOT ? 11 : 8; }
 
 // ---- cycle control kernels (one thread): everything stays on the device
 
@@ -206,9 +208,10 @@ __global__ void k_diag_final(const double* part, int nblocks, double dv, double 
 
 int hip_fail(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_HIP; }
 
-void fields_of(const mhd_state_view* v, void* out[8]) {
+void fields_of(const mhd_state_view* v, void* out[11]) {
   out[0] = v->rho; out[1] = v->mx; out[2] = v->my; out[3] = v->mz;
   out[4] = v->en; out[5] = v->bx; out[6] = v->by; out[7] = v->bz;
+  out[8] = v->ax; out[9] = v->ay; out[10] = v->az;
 }
 
 // Stage roles of one box: the buffer S_dt acts on, the buffer written and, for a
@@ -230,6 +233,7 @@ hipError_t launch_stage(mhd_ctx* const* c, const Roles* r, int n, int mode, doub
     ba.w = w;
     ba.w0 = w0;
     ba.emf = c[i0]->p.emf;
+    ba.ct = c[i0]->p.ct;
     int g = 0;
     for (int i = 0; i < m; ++i) {
       ba.desc[i] = c[i0 + i]->desc;
@@ -246,6 +250,36 @@ hipError_t launch_stage(mhd_ctx* const* c, const Roles* r, int n, int mode, doub
     hipError_t e = c0->p.precision == MHD_FP32
                        ? stage_f32(ba, c0->tile, c0->p.riemann, rc, st, false)
                        : stage_f64(ba, c0->tile, c0->p.riemann, rc, st, false);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Vector-potential form after a stage launch (mode 0: first stage, 1: combining
+// stage): A update on every edge, then the face field from curl A; update =
+// false runs only the curl (deriving B from a potential the caller set).
+hipError_t launch_vpot(mhd_ctx* const* c, const Roles* r, int n, int mode, double w, double w0,
+                       bool update, hipStream_t st) {
+  for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+    const int m = n - i0 < kMaxBatch ? n - i0 : kMaxBatch;
+    BatchArgs ba = {};
+    ba.nbox = m;
+    ba.mode = mode;
+    ba.w = w;
+    ba.w0 = w0;
+    int g = 0;
+    for (int i = 0; i < m; ++i) {
+      ba.desc[i] = c[i0 + i]->desc;
+      ba.start[i] = g;
+      ba.src[i] = r[i0 + i].src;
+      ba.dst[i] = r[i0 + i].dst;
+      ba.base[i] = r[i0 + i].base;
+      g += (int)((c[i0 + i]->ncell + kVpotBlock - 1) / kVpotBlock);
+    }
+    ba.start[m] = g;
+    ba.total = g;
+    hipError_t e = update ? vpot_update_f64(ba, st) : hipSuccess;
+    if (e == hipSuccess) e = vpot_curl_f64(ba, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -285,6 +319,7 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
     if (nsteps[i] > 0) { act[m] = c[i]; ts[m] = t_stop ? t_stop[i] : 0.0; ++m; }
   if (launch_ctl(true, act, m, ts, st) != hipSuccess) return MHD_ERR_HIP;
   const int integ = c[0]->p.integrator;
+  const bool vp = c[0]->p.ct == MHD_CT_VECPOT;
   for (int cyc = 0; cyc < maxs; ++cyc) {
     m = 0;
     for (int i = 0; i < n; ++i)
@@ -294,19 +329,24 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
       const int u0 = act[i]->cur;
       roles[i] = {(unsigned char)u0, (unsigned char)(u0 == 0 ? 1 : 0), (unsigned char)u0};
     }
-    if (launch_stage(act, roles, m, 0, 1.0, 0.0, st) != hipSuccess) return MHD_ERR_HIP;
+    // with the vector-potential form every stage is followed by the A update
+    // and the curl (same roles and weights)
+    auto stage = [&](int mode, double w, double w0) -> bool {
+      if (launch_stage(act, roles, m, mode, w, w0, st) != hipSuccess) return false;
+      return !vp || launch_vpot(act, roles, m, mode, w, w0, true, st) == hipSuccess;
+    };
+    if (!stage(0, 1.0, 0.0)) return MHD_ERR_HIP;
     if (integ == MHD_RK2) {
       // U^{n+1} = 1/2 S_dt(U_1) + 1/2 U_0, written over U_0
       for (int i = 0; i < m; ++i) roles[i] = {roles[i].dst, roles[i].src, roles[i].src};
-      if (launch_stage(act, roles, m, 1, 0.5, 0.5, st) != hipSuccess) return MHD_ERR_HIP;
+      if (!stage(1, 0.5, 0.5)) return MHD_ERR_HIP;
     } else if (integ == MHD_RK3) {
       // U_2 = 1/4 S_dt(U_1) + 3/4 U_0 into the third buffer, then
       // U^{n+1} = 2/3 S_dt(U_2) + 1/3 U_0 written over U_0 (cur is 0 here)
       for (int i = 0; i < m; ++i) roles[i] = {1, 2, 0};
-      if (launch_stage(act, roles, m, 1, 0.25, 0.75, st) != hipSuccess) return MHD_ERR_HIP;
+      if (!stage(1, 0.25, 0.75)) return MHD_ERR_HIP;
       for (int i = 0; i < m; ++i) roles[i] = {2, 0, 0};
-      if (launch_stage(act, roles, m, 1, 2.0 / 3.0, 1.0 / 3.0, st) != hipSuccess)
-        return MHD_ERR_HIP;
+      if (!stage(1, 2.0 / 3.0, 1.0 / 3.0)) return MHD_ERR_HIP;
     } else {
       for (int i = 0; i < m; ++i) act[i]->cur = roles[i].dst;
     }
@@ -337,13 +377,18 @@ int apply_shape(mhd_ctx* c, int tile, int zchunk) {
   const mhd_params* p = &c->p;
   BatchArgs none = {};
   none.emf = p->emf;
+  none.ct = p->ct;
   hipError_t e = p->precision == MHD_FP32 ? stage_f32(none, tile, p->riemann, p->recon, nullptr, true)
                                           : stage_f64(none, tile, p->riemann, p->recon, nullptr, true);
   if (e != hipSuccess) return MHD_ERR_HIP;
   const int lz = zchunk > 0 ? (zchunk < p->nz ? zchunk : p->nz) : choose_lz(tile, p->nx, p->ny, p->nz);
   BoxDesc d = {};
   for (int b = 0; b < c->nbuf; ++b)
-    for (int f = 0; f < 8; ++f) d.buf[b][f] = c->buf[b][f];
+    for (int f = 0; f < c->nfield; ++f) d.buf[b][f] = c->buf[b][f];
+  d.ct = p->ct;
+  d.b0[0] = p->b0[0];
+  d.b0[1] = p->b0[1];
+  d.b0[2] = p->b0[2];
   d.nx = p->nx;
   d.ny = p->ny;
   d.nz = p->nz;
@@ -397,7 +442,8 @@ size_t mhd_workspace_bytes(const mhd_params* p) {
   if (!grid_ok(p)) return 0;
   if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return 0;
   return align_up(sizeof(Scalars)) + align_up(sizeof(BoxDesc)) +
-         align_up(sizeof(double) * kDiagBlocks * kDiagVals) + 8 * nbuf_of(p) * field_bytes(p);
+         align_up(sizeof(double) * kDiagBlocks * kDiagVals) +
+         (size_t)nfield_of(p) * nbuf_of(p) * field_bytes(p);
 }
 
 int mhd_create(const mhd_params* p, mhd_ctx** out) {
@@ -413,6 +459,10 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH)
     return MHD_ERR_UNSUPPORTED;
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3) return MHD_ERR_UNSUPPORTED;
+  if (p->ct != MHD_CT_FACE && p->ct != MHD_CT_VECPOT) return MHD_ERR_INVALID_ARG;
+  if (p->ct == MHD_CT_VECPOT &&
+      (p->precision != MHD_FP64 || p->emf != MHD_EMF_EC || p->riemann == MHD_HLLC))
+    return MHD_ERR_UNSUPPORTED;
   if (p->integrator != MHD_RK2 && p->integrator != MHD_EULER && p->integrator != MHD_RK3)
     return MHD_ERR_INVALID_ARG;
   if (p->zchunk < 0) return MHD_ERR_INVALID_ARG;
@@ -448,8 +498,9 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   // relies on every buffer holding its fields at the same relative offsets
   const size_t fb = field_bytes(p);
   c->nbuf = nbuf_of(p);
+  c->nfield = nfield_of(p);
   for (int b = 0; b < c->nbuf; ++b)
-    for (int f = 0; f < 8; ++f) {
+    for (int f = 0; f < c->nfield; ++f) {
       c->buf[b][f] = w;
       w += fb;
     }
@@ -470,15 +521,22 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
 
 int mhd_set_state(mhd_ctx* c, const mhd_state_view* v, double t, double dt_next) {
   if (!c || !v) return MHD_ERR_INVALID_ARG;
-  void* src[8];
+  const bool vp = c->p.ct == MHD_CT_VECPOT;
+  void* src[11];
   fields_of(v, src);
-  for (int f = 0; f < 8; ++f)
-    if (!src[f]) return MHD_ERR_INVALID_ARG;
+  // the potential form takes A and derives the face field; otherwise B is given
+  for (int f = 0; f < c->nfield; ++f)
+    if (!src[f] && !(vp && f >= 5 && f < 8)) return MHD_ERR_INVALID_ARG;
   const size_t bytes = (size_t)c->ncell * c->elem;
   c->cur = 0;
-  for (int f = 0; f < 8; ++f) {
+  for (int f = 0; f < c->nfield; ++f) {
+    if (vp && f >= 5 && f < 8) continue;
     hipError_t e = hipMemcpyAsync(c->buf[0][f], src[f], bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return MHD_ERR_HIP;
+  }
+  if (vp) {
+    const Roles r0 = {0, 0, 0};
+    if (launch_vpot(&c, &r0, 1, 0, 1.0, 0.0, false, c->stream) != hipSuccess) return MHD_ERR_HIP;
   }
   hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, c->stream, c->sc, t, dt_next, c->p.cfl);
   if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
@@ -500,11 +558,14 @@ int mhd_step(mhd_ctx* c, int nsteps, double t_stop) {
 int mhd_get_state(mhd_ctx* c, const mhd_state_view* v, double* t, double* dt_next) {
   if (!c) return MHD_ERR_INVALID_ARG;
   if (v) {
-    void* dst[8];
+    void* dst[11];
     fields_of(v, dst);
     const size_t bytes = (size_t)c->ncell * c->elem;
-    for (int f = 0; f < 8; ++f) {
+    for (int f = 0; f < 8; ++f)
       if (!dst[f]) return MHD_ERR_INVALID_ARG;
+    // the potential is copied out when the view asks for it
+    const int nf = c->nfield == 11 && dst[8] && dst[9] && dst[10] ? 11 : 8;
+    for (int f = 0; f < nf; ++f) {
       hipError_t e = hipMemcpyAsync(dst[f], c->buf[c->cur][f], bytes, hipMemcpyDeviceToDevice, c->stream);
       if (e != hipSuccess) return MHD_ERR_HIP;
     }

@@ -54,13 +54,18 @@ enum { TILE_16x16 = 1, TILE_24x8 = 2 };
 // One box as the stage kernel sees it; each context keeps its descriptor in its
 // own workspace (rewritten only when its launch shape changes).
 constexpr int kMaxBuf = 3;  // state buffers: U_0 and up to two stage results
+// fields of a buffer: rho mx my mz en bx by bz, and with the vector-potential
+// form of constrained transport the edge potential ax ay az
+constexpr int kFields = 11;
+enum { CT_FACE = 0, CT_VECPOT = 1 };
 struct BoxDesc {
-  void* buf[kMaxBuf][8];  // state buffers: rho mx my mz en bx by bz
+  void* buf[kMaxBuf][kFields];
   int nx, ny, nz;
   int ntx, nty, nzc, lz;  // tiles of the context's tile shape, z-chunks
-  int pad;
+  int ct;                 // CT_FACE or CT_VECPOT
   double idl[3];          // 1 / dl_d
   double gamma;
+  double b0[3];           // mean field of the vector-potential form
   Scalars* sc;
 };
 
@@ -72,6 +77,8 @@ constexpr int kMaxBatch = 64;
 struct BatchArgs {
   int nbox, mode, total;
   int emf;  // corner-EMF scheme shared by the batch
+  int ct;   // CT_FACE or CT_VECPOT, shared by the batch
+  int pad;
   double w, w0;
   const BoxDesc* desc[kMaxBatch];
   int start[kMaxBatch + 1];
@@ -81,6 +88,12 @@ struct BatchArgs {
 // stage launch for one precision (mhd_stage_f64.hip / mhd_stage_f32.hip)
 hipError_t stage_f64(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
                      bool prepare);
+// vector-potential form (FP64): A_dst = w (A_src - dt E) + w0 A_base on every
+// edge, with E left in the output's face-field slots by the stage kernel, then
+// B_dst = b0 + curl A_dst.  ba.start[] counts blocks of kVpotBlock cells.
+constexpr int kVpotBlock = 256;
+hipError_t vpot_update_f64(const BatchArgs& b, hipStream_t st);
+hipError_t vpot_curl_f64(const BatchArgs& b, hipStream_t st);
 hipError_t stage_f32(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
                      bool prepare);
 int tile_dims(int tile, int* tx, int* ty);

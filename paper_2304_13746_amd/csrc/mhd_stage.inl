@@ -259,7 +259,7 @@ struct Occupancy {
   static constexpr int waves = sizeof(R) == 4 ? MHD_WAVES_F32 : MHD_WAVES_F64;
 };
 
-template <typename R, int SOLVER, int RECON, int EMF, int MODE, int TX, int TY>
+template <typename R, int SOLVER, int RECON, int EMF, int CT, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY + 2 * (TX + TY))
 __attribute__((amdgpu_waves_per_eu(Occupancy<R>::waves)))
 stage_kernel(BatchArgs ba) {
@@ -599,19 +599,23 @@ stage_kernel(BatchArgs ba) {
         R un[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) un[q] = pt_(q) - tau_z * (fz.cons[q] - fzp(q));
-        const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
-        R bxn = (gld(a.src[5], o) - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
-        R byn = (gld(a.src[6], o) - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
         if constexpr (MODE == MODE_COMBINE) {
 #pragma unroll
           for (int q = 0; q < 5; ++q) un[q] = a.w * un[q] + a.w0 * gld<R>(a.dst[q], o + a.boff);
-          bxn = a.w * bxn + a.w0 * gld<R>(a.dst[5], o + a.boff);
-          byn = a.w * byn + a.w0 * gld<R>(a.dst[6], o + a.boff);
         }
 #pragma unroll
         for (int q = 0; q < 5; ++q) gst(a.dst[q], o, un[q]);
-        gst(a.dst[5], o, bxn);
-        gst(a.dst[6], o, byn);
+        if constexpr (CT == CT_FACE) {
+          const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
+          R bxn = (gld(a.src[5], o) - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
+          R byn = (gld(a.src[6], o) - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
+          if constexpr (MODE == MODE_COMBINE) {
+            bxn = a.w * bxn + a.w0 * gld<R>(a.dst[5], o + a.boff);
+            byn = a.w * byn + a.w0 * gld<R>(a.dst[6], o + a.boff);
+          }
+          gst(a.dst[5], o, bxn);
+          gst(a.dst[6], o, byn);
+        }
       }
     }
     __syncthreads();  // reads of corner-EMF buffers of plane m-1 done
@@ -624,10 +628,19 @@ stage_kernel(BatchArgs ba) {
     if constexpr (MODE != MODE_MEASURE) {
       if (real && m >= z0 && m < z1) {
         const long long o = (long long)km * plane + col;
-        const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
-        R bzn = (bz_m - tau_x * (S.ey[e_e] - ey_new)) + tau_y * (S.ex[e_n] - ex_new);
-        if constexpr (MODE == MODE_COMBINE) bzn = a.w * bzn + a.w0 * gld<R>(a.dst[7], o + a.boff);
-        gst(a.dst[7], o, bzn);
+        if constexpr (CT == CT_FACE) {
+          const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
+          R bzn = (bz_m - tau_x * (S.ey[e_e] - ey_new)) + tau_y * (S.ex[e_n] - ex_new);
+          if constexpr (MODE == MODE_COMBINE) bzn = a.w * bzn + a.w0 * gld<R>(a.dst[7], o + a.boff);
+          gst(a.dst[7], o, bzn);
+        } else {
+          // vector-potential form: leave this column's three corner EMFs of
+          // index (i, j, m) in the output's face-field slots; the potential
+          // update and the curl follow in their own launches
+          gst(a.dst[5], o, ex_new);
+          gst(a.dst[6], o, ey_new);
+          gst(a.dst[7], o, ez_new);
+        }
       }
     }
 
@@ -669,11 +682,11 @@ stage_kernel(BatchArgs ba) {
 
 // Launch one instantiation.  With prepare = true only raise its dynamic-LDS
 // limit (a host-side attribute, done when a context takes a launch shape).
-template <typename R, int SOLVER, int RECON, int EMF, int MODE, int TX, int TY>
+template <typename R, int SOLVER, int RECON, int EMF, int CT, int MODE, int TX, int TY>
 static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) {
   using T = Tile<TX, TY>;
   const size_t lds = sizeof(SmemAll<R, TX, TY>);
-  auto fn = stage_kernel<R, SOLVER, RECON, EMF, MODE, TX, TY>;
+  auto fn = stage_kernel<R, SOLVER, RECON, EMF, CT, MODE, TX, TY>;
   if (prepare)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -681,20 +694,28 @@ static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) 
   return hipGetLastError();
 }
 
-template <typename R, int SOLVER, int RECON, int EMF, int TX, int TY>
+template <typename R, int SOLVER, int RECON, int EMF, int CT, int TX, int TY>
 static hipError_t launch_mode(const BatchArgs& ba, hipStream_t st, bool prepare) {
   if (ba.mode == MODE_STAGE1)
-    return launch_one<R, SOLVER, RECON, EMF, MODE_STAGE1, TX, TY>(ba, st, prepare);
+    return launch_one<R, SOLVER, RECON, EMF, CT, MODE_STAGE1, TX, TY>(ba, st, prepare);
   if (ba.mode == MODE_COMBINE)
-    return launch_one<R, SOLVER, RECON, EMF, MODE_COMBINE, TX, TY>(ba, st, prepare);
-  return launch_one<R, SOLVER, RECON, EMF, MODE_MEASURE, TX, TY>(ba, st, prepare);
+    return launch_one<R, SOLVER, RECON, EMF, CT, MODE_COMBINE, TX, TY>(ba, st, prepare);
+  return launch_one<R, SOLVER, RECON, EMF, CT, MODE_MEASURE, TX, TY>(ba, st, prepare);
 }
 
+// The vector-potential form is built for FP64 with the default EMF scheme.
 template <typename R, int SOLVER, int RECON, int TX, int TY>
 static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) {
-  if (ba.emf == EMF_E0) return launch_mode<R, SOLVER, RECON, EMF_E0, TX, TY>(ba, st, prepare);
-  if (ba.emf == EMF_ARITH) return launch_mode<R, SOLVER, RECON, EMF_ARITH, TX, TY>(ba, st, prepare);
-  return launch_mode<R, SOLVER, RECON, EMF_EC, TX, TY>(ba, st, prepare);
+  if (ba.ct == CT_VECPOT) {
+    if constexpr (sizeof(R) == 8) {
+      if (ba.emf == EMF_EC) return launch_mode<R, SOLVER, RECON, EMF_EC, CT_VECPOT, TX, TY>(ba, st, prepare);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (ba.emf == EMF_E0) return launch_mode<R, SOLVER, RECON, EMF_E0, CT_FACE, TX, TY>(ba, st, prepare);
+  if (ba.emf == EMF_ARITH)
+    return launch_mode<R, SOLVER, RECON, EMF_ARITH, CT_FACE, TX, TY>(ba, st, prepare);
+  return launch_mode<R, SOLVER, RECON, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
 }
 
 template <typename R, int TX, int TY>
@@ -708,15 +729,17 @@ static hipError_t launch_tile(const BatchArgs& ba, int solver, int recon, hipStr
     return lim ? launch_emf<R, SOLVER_HLL, RECON_LIMO3, TX, TY>(ba, st, prepare)
                : launch_emf<R, SOLVER_HLL, RECON_PLM, TX, TY>(ba, st, prepare);
   // HLLC (B = 0 problems): the EMFs vanish, so only the default scheme is built
-  return lim ? launch_mode<R, SOLVER_HLLC, RECON_LIMO3, EMF_EC, TX, TY>(ba, st, prepare)
-             : launch_mode<R, SOLVER_HLLC, RECON_PLM, EMF_EC, TX, TY>(ba, st, prepare);
+  if (ba.ct != CT_FACE) return hipErrorInvalidValue;
+  return lim ? launch_mode<R, SOLVER_HLLC, RECON_LIMO3, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare)
+             : launch_mode<R, SOLVER_HLLC, RECON_PLM, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
 }
 
 // Raise the LDS limit of every mode of one (solver, reconstruction, EMF) choice.
 template <typename R, int TX, int TY>
-static hipError_t prepare_tile(int solver, int recon, int emf) {
+static hipError_t prepare_tile(int solver, int recon, int emf, int ct) {
   BatchArgs ba = {};
   ba.emf = emf;
+  ba.ct = ct;
   for (int mode = 0; mode < 3; ++mode) {
     ba.mode = mode;
     hipError_t e = launch_tile<R, TX, TY>(ba, solver, recon, nullptr, true);

@@ -5,12 +5,12 @@ namespace mhd {
 template <typename R>
 static hipError_t stage_launch(const BatchArgs& ba, int tile, int solver, int recon,
                                hipStream_t st, bool prepare) {
-  // with prepare, ba.emf names the EMF scheme whose kernels are prepared
+  // with prepare, ba.emf and ba.ct name the kernels to prepare
   int tx, ty;
   if (!tile_dims(tile, &tx, &ty)) return hipErrorInvalidValue;
   if (prepare) {
-    if (tile == TILE_16x16) return prepare_tile<R, 16, 16>(solver, recon, ba.emf);
-    return prepare_tile<R, 24, 8>(solver, recon, ba.emf);
+    if (tile == TILE_16x16) return prepare_tile<R, 16, 16>(solver, recon, ba.emf, ba.ct);
+    return prepare_tile<R, 24, 8>(solver, recon, ba.emf, ba.ct);
   }
   if (ba.nbox < 1 || ba.nbox > kMaxBatch || ba.total < 1) return hipErrorInvalidValue;
   if (tile == TILE_16x16) return launch_tile<R, 16, 16>(ba, solver, recon, st, false);

@@ -1,0 +1,97 @@
+"""The vector-potential form of constrained transport on the GPU (Sec. 2.4,
+eqs. ind_vec): bit-identical to the oracle's potential form in FP64 (state,
+potential and dt sequence), alone and in a batch; FP32 is refused."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import FIELDS, bit_equal, need_gpu
+from paper_2304_13746_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+POT = ("ax", "ay", "az")
+
+
+def copy_pot(a):
+    return {"ax": a["ax"].copy(), "ay": a["ay"].copy(), "az": a["az"].copy(), "b0": a["b0"]}
+
+
+def gpu_run(s, a, dims, l, nsteps, integrator="rk2", riemann="hlld", stream=None):
+    from paper_2304_13746_amd.box import MHDBox
+    box = MHDBox(*dims, *l, integrator=integrator, riemann=riemann, ct="vecpot", b0=a["b0"],
+                 stream=stream)
+    st = dict(s)
+    st.update({k: a[k] for k in POT})
+    box.set_state(st)
+    dts = []
+    for _ in range(nsteps):
+        box.step(1)
+        dts.append(box.get_state()[2])
+    g, t, dt, rc = box.get_state_numpy()
+    assert rc == 0
+    return g, t, dts
+
+
+@pytest.mark.parametrize("integrator", ["rk2", "rk3"])
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+def test_vecpot_fp64_bit_exact(integrator, riemann):
+    need_gpu()
+    n = 24
+    s, a = I.orszag_tang_3d(n, potential=True)
+    dims, l = (n, n, n), (1.0, 1.0, 1.0)
+    g, tg, gd = gpu_run(s, a, dims, l, 5, integrator, riemann)
+    o, ao = O.copy_state(s), copy_pot(a)
+    p = O.Params(n, n, n, integrator={"rk2": O.RK2, "rk3": O.RK3}[integrator],
+                 riemann={"hlld": O.HLLD, "hll": O.HLL}[riemann])
+    t, dt = 0.0, 0.0
+    od = []
+    for _ in range(5):
+        t, dt, _ = O.step_vp(p, o, ao, t, dt, 1)
+        od.append(dt)
+    o.update({k: ao[k] for k in POT})
+    for f in FIELDS + POT:
+        assert np.array_equal(g[f], o[f]), f
+    assert gd == od and tg == t
+
+
+def test_vecpot_mean_field_ragged_batch():
+    """Ragged turbulent boxes with a mean field (A = 0 initially, b0 carried):
+    a batch equals each box alone, and the first box equals the oracle."""
+    torch = need_gpu()
+    from paper_2304_13746_amd.batch import BoxBatch
+    from paper_2304_13746_amd.box import MHDBox
+    specs = []
+    for dims, seed in (((40, 24, 18), 3), ((16, 32, 24), 4)):
+        s = I.turbulence(dims, seed=seed, kpeak=2.0, mach=0.8, b0=(0.2, -0.1, 0.3))
+        l = s.pop("_l")
+        specs.append((dims, l, s, I.uniform_field_potential(s["rho"].shape, (0.2, -0.1, 0.3))))
+    stream = torch.cuda.Stream()
+    boxes = []
+    for dims, l, s, a in specs:
+        bx = MHDBox(*dims, *l, ct="vecpot", b0=a["b0"], stream=stream)
+        st = dict(s)
+        st.update({k: a[k] for k in POT})
+        bx.set_state(st)
+        boxes.append(bx)
+    BoxBatch(boxes).step([3, 4])
+    for (dims, l, s, a), bx, k in zip(specs, boxes, (3, 4)):
+        g, t, dts = gpu_run(s, a, dims, l, k)
+        b, tb, _, _ = bx.get_state_numpy()
+        assert bit_equal(g, b) and t == tb
+        for f in POT:
+            assert np.array_equal(g[f], b[f])
+    dims, l, s, a = specs[0]
+    g, t, _ = gpu_run(s, a, dims, l, 3)
+    o, ao = O.copy_state(s), copy_pot(a)
+    O.step_vp(O.Params(*dims, *l), o, ao, 0.0, 0.0, 3)
+    assert bit_equal(g, o)
+    for f in POT:
+        assert np.array_equal(g[f], ao[f])
+
+
+def test_vecpot_fp32_is_refused():
+    need_gpu()
+    from paper_2304_13746_amd import _lib as L
+    from paper_2304_13746_amd.box import MHDBox
+    with pytest.raises(L.MHDError):
+        MHDBox(16, 16, 16, precision="fp32", ct="vecpot")
