@@ -72,7 +72,7 @@ typedef struct mhd_ctx mhd_ctx; /* opaque */
 
 /* Stage-kernel tile: the x-by-y column block one work-group owns (plus a
  * one-cell ring).  Results do not depend on it (bit-identical in FP64). */
-enum { MHD_TILE_DEFAULT = 0, MHD_TILE_16x16 = 1, MHD_TILE_24x8 = 2 };
+enum { MHD_TILE_DEFAULT = 0, MHD_TILE_16x16 = 1, MHD_TILE_24x8 = 2, MHD_TILE_18x11 = 3 };
 
 typedef struct {
   int nx, ny, nz;         /* cells per direction, each in [1, 4096] */

@@ -25,7 +25,7 @@ MHD_EMF_EC, MHD_EMF_E0, MHD_EMF_ARITH = 0, 1, 2
 MHD_PLM, MHD_LIMO3 = 0, 1
 MHD_CT_FACE, MHD_CT_VECPOT = 0, 1
 MHD_RK2, MHD_EULER, MHD_RK3 = 0, 1, 2
-TILE_16x16, TILE_24x8 = 1, 2
+TILE_16x16, TILE_24x8, TILE_18x11 = 1, 2, 3
 
 EXPORTED = ("mhd_workspace_bytes", "mhd_create", "mhd_set_state", "mhd_step", "mhd_get_state",
             "mhd_get_diagnostics", "mhd_step_batch", "mhd_set_launch", "mhd_get_launch", "mhd_tune",

@@ -21,7 +21,7 @@ import threading
 
 from . import _lib as L
 
-TILE_NAMES = {L.TILE_16x16: "16x16", L.TILE_24x8: "24x8"}
+TILE_NAMES = {L.TILE_16x16: "16x16", L.TILE_24x8: "24x8", L.TILE_18x11: "18x11"}
 
 
 def default_cache_path() -> str:

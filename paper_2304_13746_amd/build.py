@@ -14,6 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmhd.so")
+# a plain host program that drives the library through the C ABI only
+EXAMPLE = os.path.join(HERE, "mhd_abi_example")
 SOURCES = ["mhd_api.hip", "mhd_stage_f64.hip", "mhd_stage_f32.hip", "mhd_vpot.hip"]
 ARCH = os.environ.get("MHD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -48,6 +50,13 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, out)
+    if out == LIB:
+        cmd = [HIPCC, "-O2", "-std=c++17", os.path.join(CSRC, "mhd_abi_example.cpp"), "-o",
+               EXAMPLE + ".tmp", "-L" + HERE, "-lmhd", "-Wl,-rpath,$ORIGIN"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"building the C ABI example failed:\n{r.stderr}")
+        os.replace(EXAMPLE + ".tmp", EXAMPLE)
     if verbose:
         print("built", out)
     return out

@@ -427,6 +427,7 @@ namespace mhd {
 int tile_dims(int tile, int* tx, int* ty) {
   if (tile == TILE_16x16) { *tx = 16; *ty = 16; return 1; }
   if (tile == TILE_24x8) { *tx = 24; *ty = 8; return 1; }
+  if (tile == TILE_18x11) { *tx = 18; *ty = 11; return 1; }
   return 0;
 }
 int stage_blocks(int tile, int nx, int ny, int nz, int lz) {
@@ -644,7 +645,7 @@ int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_resul
     if (!ctxs[i]) return MHD_ERR_INVALID_ARG;
   if (!same_group(ctxs, n)) return MHD_ERR_UNSUPPORTED;
   hipStream_t st = stream ? (hipStream_t)stream : ctxs[0]->stream;
-  static const int tiles[] = {TILE_24x8, TILE_16x16};
+  static const int tiles[] = {TILE_24x8, TILE_18x11, TILE_16x16};
   static const int caps[] = {0, 8, 16, 32, 64, 128};
   const int ntile = sizeof(tiles) / sizeof(tiles[0]), ncap = sizeof(caps) / sizeof(caps[0]);
   Roles* src = (Roles*)malloc(sizeof(Roles) * n);

@@ -49,7 +49,7 @@ __device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
 }
 
 // Tile variants of the stage kernel.
-enum { TILE_16x16 = 1, TILE_24x8 = 2 };
+enum { TILE_16x16 = 1, TILE_24x8 = 2, TILE_18x11 = 3 };
 
 // One box as the stage kernel sees it; each context keeps its descriptor in its
 // own workspace (rewritten only when its launch shape changes).

@@ -86,7 +86,9 @@ class Server:
         self.skip_ahead = skip_ahead
         self.inflight_max = inflight
 
-    def run(self, requests, keep_results: bool = False):
+    def run(self, requests, keep_results: bool = False, progress=None):
+        """Serve ``requests`` to completion; ``progress(done, total)`` is called
+        after every retirement when given."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue: deque[Request] = deque()
         active: list[_Active] = []
@@ -140,6 +142,8 @@ class Server:
                                      res if keep_results else None))
                     used -= a.nbytes
                     active.remove(a)
+                if progress is not None:
+                    progress(len(done), len(requests))
                 continue
             # idle: wait for the GPU or the next arrival
             if inflight:

@@ -117,7 +117,7 @@ def test_nonphysical_state_is_latched_and_reported():
     assert rc == _lib.MHD_OK
 
 
-@pytest.mark.parametrize("tile,zchunk", [(1, 16), (1, 7), (2, 32), (2, 3)])
+@pytest.mark.parametrize("tile,zchunk", [(1, 16), (1, 7), (2, 32), (2, 3), (3, 0), (3, 5)])
 def test_launch_shape_invariance_fp64(tile, zchunk):
     """Tile shape and z-chunk length change only how work is split: FP64
     results are bit-identical to the oracle for every launch shape."""
