@@ -53,7 +53,8 @@ extern "C" {
 
 typedef enum { MHD_FP64 = 0, MHD_FP32 = 1 } mhd_precision;
 /* Riemann solvers of Sec. 2.3; HLLC is the hydrodynamic solver for B = 0
- * problems (it ignores the field: zero B fluxes, no magnetic pressure). */
+ * problems: with it the field is neither read nor evolved (the face field is
+ * written as zero), and the stage kernel skips the EMF work entirely. */
 typedef enum { MHD_HLLD = 0, MHD_HLL = 1, MHD_HLLC = 2 } mhd_riemann;
 /* Corner-EMF schemes of Sec. 2.4 (Gardiner & Stone 2005): E^c (default), E^0
  * and the arithmetic mean of the four face EMFs. */

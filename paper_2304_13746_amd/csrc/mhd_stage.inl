@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "mhd_device.h"
 #include "mhd_internal.h"
 
@@ -104,7 +106,7 @@ struct Raw {
   R rho, mx, my, mz, en, bxl, bxr, byl, byr, bzl, bzr;
 };
 
-template <typename R>
+template <bool HY, typename R>
 __device__ __forceinline__ void load_raw(const StageArgs<R>& a, int gi, int gi1, int gj, int gj1,
                                          int gk, int gk1, Raw<R>& r) {
   const long long plane = (long long)a.nx * a.ny;
@@ -114,6 +116,10 @@ __device__ __forceinline__ void load_raw(const StageArgs<R>& a, int gi, int gi1,
   r.my = gld(a.src[2], o);
   r.mz = gld(a.src[3], o);
   r.en = gld(a.src[4], o);
+  if constexpr (HY) {  // hydrodynamics: no field
+    r.bxl = r.bxr = r.byl = r.byr = r.bzl = r.bzr = R(0);
+    return;
+  }
   r.bxl = gld(a.src[5], o);
   r.bxr = gld(a.src[5], o - gi + gi1);
   r.byl = gld(a.src[6], o);
@@ -240,33 +246,71 @@ struct Carry {
   R part[5][N], fzp[5][N];
 };
 
+// The hydrodynamic layout (HLLC, B = 0): primitives rho, v, p and the flux
+// exports of the divergence and the CFL condition only.
 template <typename R, int TX, int TY>
+struct SmemHydro {
+  using T = Tile<TX, TY>;
+  R w[5][T::NW];
+  R xcons[5][T::NE], xcmax[T::NE];
+  R ycons[5][T::NE], ycmax[T::NE];
+};
+
+template <typename R, int TX, int TY, bool HY>
 struct SmemAll {
-  Smem<R, TX, TY> s;
+  std::conditional_t<HY, SmemHydro<R, TX, TY>, Smem<R, TX, TY>> s;
   Carry<R, TX, TY> c;
 };
 
+// Primitive plane entries in LDS (the hydrodynamic layout keeps no field).
+template <bool HY, typename SM, typename R>
+__device__ __forceinline__ void put_cell(SM& S, int iw, const Cell<R>& c) {
+  S.w[0][iw] = c.rho; S.w[1][iw] = c.vx; S.w[2][iw] = c.vy; S.w[3][iw] = c.vz;
+  if constexpr (HY) {
+    S.w[4][iw] = c.p;
+  } else {
+    S.w[4][iw] = c.bx; S.w[5][iw] = c.by; S.w[6][iw] = c.bz; S.w[7][iw] = c.p;
+  }
+}
+template <bool HY, typename SM, typename R>
+__device__ __forceinline__ void get_cell(const SM& S, int iw, Cell<R>& c) {
+  c.rho = S.w[0][iw]; c.vx = S.w[1][iw]; c.vy = S.w[2][iw]; c.vz = S.w[3][iw];
+  if constexpr (HY) {
+    c.bx = c.by = c.bz = R(0);
+    c.p = S.w[4][iw];
+  } else {
+    c.bx = S.w[4][iw]; c.by = S.w[5][iw]; c.bz = S.w[6][iw]; c.p = S.w[7][iw];
+  }
+}
+
 // Waves per SIMD the register allocation must allow: FP32 three (<= 168
-// VGPRs, three 4-wave blocks per CU), FP64 two (<= 256 VGPRs).
+// VGPRs, three 4-wave blocks per CU), FP64 two (<= 256 VGPRs); one more for
+// the hydrodynamic path.
 #ifndef MHD_WAVES_F32
 #define MHD_WAVES_F32 3
 #endif
 #ifndef MHD_WAVES_F64
 #define MHD_WAVES_F64 2
 #endif
-template <typename R>
+// The hydrodynamic path (no field, no EMFs) fits one more wave per SIMD.
+template <typename R, bool HY>
 struct Occupancy {
-  static constexpr int waves = sizeof(R) == 4 ? MHD_WAVES_F32 : MHD_WAVES_F64;
+  static constexpr int waves = (sizeof(R) == 4 ? MHD_WAVES_F32 : MHD_WAVES_F64) + (HY ? 1 : 0);
 };
 
 template <typename R, int SOLVER, int RECON, int EMF, int CT, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY + 2 * (TX + TY))
-__attribute__((amdgpu_waves_per_eu(Occupancy<R>::waves)))
+__attribute__((amdgpu_waves_per_eu(Occupancy<R, SOLVER == SOLVER_HLLC>::waves)))
 stage_kernel(BatchArgs ba) {
   using T = Tile<TX, TY>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  SmemAll<R, TX, TY>& SA = *reinterpret_cast<SmemAll<R, TX, TY>*>(smem_raw);
-  Smem<R, TX, TY>& S = SA.s;
+  // HLLC is the hydrodynamic path: no field is read, no EMF is formed, the face
+  // field is written as zero, and the ring columns solve only the x- and
+  // y-faces the tile's own cells need
+  constexpr bool HY = SOLVER == SOLVER_HLLC;
+  using SA_t = SmemAll<R, TX, TY, HY>;
+  SA_t& SA = *reinterpret_cast<SA_t*>(smem_raw);
+  auto& S = SA.s;
   constexpr bool CL = Carry<R, TX, TY>::in_lds;
 
   // XCD-aware order: the hardware deals blocks round-robin over 8 XCDs; give
@@ -321,15 +365,15 @@ stage_kernel(BatchArgs ba) {
   const bool interior = ci >= 0 && ci < TX && cj >= 0 && cj < TY;
   const bool real = interior && (x0 + ci < a.nx) && (y0 + cj < a.ny);
   const bool left = ci == -1, right = ci == TX, bottom = cj == -1, top = cj == TY;
-  const bool do_x = !left;                   // own x-face (ci-1/2, cj)
-  const bool do_y = !bottom;                 // own y-face (ci, cj-1/2)
+  const bool do_x = HY ? (interior || right) : !left;   // own x-face (ci-1/2, cj)
+  const bool do_y = HY ? (interior || top) : !bottom;   // own y-face (ci, cj-1/2)
   const bool do_ez = !left && !bottom;       // E_z at (ci-1/2, cj-1/2)
   const bool do_ex = interior || top;        // E_x at (ci, cj-1/2)
   const bool do_ey = interior || right;      // E_y at (ci-1/2, cj)
   // corner faces: the first left-ring thread solves x-face (TX, -1), the first
   // bottom-ring thread y-face (-1, TY)
-  const bool corner_x = (t == TX * TY);
-  const bool corner_y = (t == TX * TY + 2 * TY);
+  const bool corner_x = !HY && (t == TX * TY);
+  const bool corner_y = !HY && (t == TX * TY + 2 * TY);
   const int ex_me = T::e(ci, cj);
 
   // halo primitive item of this thread (if any)
@@ -370,23 +414,21 @@ stage_kernel(BatchArgs ba) {
   {
     Raw<R> r;
     int k = wrapi(z0 - 2, a.nz);
-    load_raw(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
+    load_raw<HY>(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
     Cell<R> w0;
     to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w0);
     frame_vals<2>(w0, zm1);
     k = wrapi(z0 - 1, a.nz);
-    load_raw(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
+    load_raw<HY>(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
     to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w0);
     const int iw = T::w(ci, cj);
-    S.w[0][iw] = w0.rho; S.w[1][iw] = w0.vx; S.w[2][iw] = w0.vy; S.w[3][iw] = w0.vz;
-    S.w[4][iw] = w0.bx; S.w[5][iw] = w0.by; S.w[6][iw] = w0.bz; S.w[7][iw] = w0.p;
+    put_cell<HY>(S, iw, w0);
     if (has_extra) {
       Cell<R> c;
-      load_raw(a, xgi, xgi1, xgj, xgj1, k, wrapi(k + 1, a.nz), r);
+      load_raw<HY>(a, xgi, xgi1, xgj, xgj1, k, wrapi(k + 1, a.nz), r);
       to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, c);
       const int jw = T::w(xci, xcj);
-      S.w[0][jw] = c.rho; S.w[1][jw] = c.vx; S.w[2][jw] = c.vy; S.w[3][jw] = c.vz;
-      S.w[4][jw] = c.bx; S.w[5][jw] = c.by; S.w[6][jw] = c.bz; S.w[7][jw] = c.p;
+      put_cell<HY>(S, jw, c);
       erz_extra = c.vy * c.bx - c.vx * c.by;
     }
     for (int v = 0; v < 7; ++v) top7[v] = 0;
@@ -404,8 +446,7 @@ stage_kernel(BatchArgs ba) {
       for (int s = 0; s < 4; ++s) {
         Cell<R> c;
         const int iw = T::w(fi - 2 + s, fj);
-        c.rho = S.w[0][iw]; c.vx = S.w[1][iw]; c.vy = S.w[2][iw]; c.vz = S.w[3][iw];
-        c.bx = S.w[4][iw]; c.by = S.w[5][iw]; c.bz = S.w[6][iw]; c.p = S.w[7][iw];
+        get_cell<HY>(S, iw, c);
         frame_vals<0>(c, q[s]);
       }
       R ql[7], qr[7];
@@ -414,17 +455,23 @@ stage_kernel(BatchArgs ba) {
         ql[v] = recon_hi<RECON>(q[0][v], q[1][v], q[2][v]);
         qr[v] = recon_lo<RECON>(q[1][v], q[2][v], q[3][v]);
       }
-      R bn;
-      if (corner_x) {
-        const long long o = (long long)km * a.nx * a.ny + (long long)wrapi(y0 - 1, a.ny) * a.nx +
-                            wrapi(x0 + TX, a.nx);
-        bn = gld(a.src[5], o);
-      } else {
-        bn = gld(a.src[5], (long long)km * plane + col);
+      R bn = R(0);
+      if constexpr (!HY) {
+        if (corner_x) {
+          const long long o = (long long)km * a.nx * a.ny + (long long)wrapi(y0 - 1, a.ny) * a.nx +
+                              wrapi(x0 + TX, a.nx);
+          bn = gld(a.src[5], o);
+        } else {
+          bn = gld(a.src[5], (long long)km * plane + col);
+        }
       }
       solve_face<0, SOLVER>(a, ql, qr, bn, fx);
       // the previous plane's exports were consumed before the last barrier
-      if (corner_x) {
+      if constexpr (HY) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) S.xcons[q][ex_me] = fx.cons[q];
+        S.xcmax[ex_me] = fx.cmax;
+      } else if (corner_x) {
         const int ec = T::e(TX, -1);
         S.xez[ec] = -fx.fb1;
         S.xmass[ec] = fx.cons[0];
@@ -443,8 +490,7 @@ stage_kernel(BatchArgs ba) {
       for (int s = 0; s < 4; ++s) {
         Cell<R> c;
         const int iw = T::w(fi, fj - 2 + s);
-        c.rho = S.w[0][iw]; c.vx = S.w[1][iw]; c.vy = S.w[2][iw]; c.vz = S.w[3][iw];
-        c.bx = S.w[4][iw]; c.by = S.w[5][iw]; c.bz = S.w[6][iw]; c.p = S.w[7][iw];
+        get_cell<HY>(S, iw, c);
         frame_vals<1>(c, q[s]);
       }
       R ql[7], qr[7];
@@ -453,16 +499,22 @@ stage_kernel(BatchArgs ba) {
         ql[v] = recon_hi<RECON>(q[0][v], q[1][v], q[2][v]);
         qr[v] = recon_lo<RECON>(q[1][v], q[2][v], q[3][v]);
       }
-      R bn;
-      if (corner_y) {
-        const long long o = (long long)km * a.nx * a.ny + (long long)wrapi(y0 + TY, a.ny) * a.nx +
-                            wrapi(x0 - 1, a.nx);
-        bn = gld(a.src[6], o);
-      } else {
-        bn = gld(a.src[6], (long long)km * plane + col);
+      R bn = R(0);
+      if constexpr (!HY) {
+        if (corner_y) {
+          const long long o = (long long)km * a.nx * a.ny + (long long)wrapi(y0 + TY, a.ny) * a.nx +
+                              wrapi(x0 - 1, a.nx);
+          bn = gld(a.src[6], o);
+        } else {
+          bn = gld(a.src[6], (long long)km * plane + col);
+        }
       }
       solve_face<1, SOLVER>(a, ql, qr, bn, fy);
-      if (corner_y) {
+      if constexpr (HY) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) S.ycons[q][ex_me] = fy.cons[q];
+        S.ycmax[ex_me] = fy.cmax;
+      } else if (corner_y) {
         const int ec = T::e(-1, TY);
         S.yez[ec] = fy.fb2;
         S.ymass[ec] = fy.cons[0];
@@ -483,26 +535,25 @@ stage_kernel(BatchArgs ba) {
     {
       Raw<R> r;
       const int kn = wrapi(m + 1, a.nz);
-      load_raw(a, gi, gi1, gj, gj1, kn, wrapi(kn + 1, a.nz), r);
+      load_raw<HY>(a, gi, gi1, gj, gj1, kn, wrapi(kn + 1, a.nz), r);
       to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w1);
     }
     // own primitives of plane m, still in the LDS plane
     Cell<R> w0;
     {
       const int iw = T::w(ci, cj);
-      w0.rho = S.w[0][iw]; w0.vx = S.w[1][iw]; w0.vy = S.w[2][iw]; w0.vz = S.w[3][iw];
-      w0.bx = S.w[4][iw]; w0.by = S.w[5][iw]; w0.bz = S.w[6][iw]; w0.p = S.w[7][iw];
+      get_cell<HY>(S, iw, w0);
     }
-    const R bz_m = gld(a.src[7], (long long)km * plane + col);
+    const R bz_m = HY ? R(0) : gld(a.src[7], (long long)km * plane + col);
     Cell<R> wx;  // halo item of plane m+1
     if (has_extra) {
       Raw<R> r;
       const int kn = wrapi(m + 1, a.nz);
-      load_raw(a, xgi, xgi1, xgj, xgj1, kn, wrapi(kn + 1, a.nz), r);
+      load_raw<HY>(a, xgi, xgi1, xgj, xgj1, kn, wrapi(kn + 1, a.nz), r);
       to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, wx);
     }
     Face<R> fz = {};
-    {
+    if (!HY || interior) {  // hydrodynamics needs the z-faces of its own cells only
       R qa[7], qb[7], qc[7];
 #pragma unroll
       for (int v = 0; v < 7; ++v) qa[v] = zm1[v];
@@ -529,31 +580,32 @@ stage_kernel(BatchArgs ba) {
     const R erz = w0.vy * w0.bx - w0.vx * w0.by;
     if (real && m >= z0 && m < z1) bad |= bad_cell(w0);
 
-    S.zex[ex_me] = fz.fb2;
-    S.zey[ex_me] = -fz.fb1;
-    S.zmass[ex_me] = fz.cons[0];
-    S.erz[ex_me] = erz;
-    S.erx[ex_me] = erx;
-    S.erxp[ex_me] = erx_prev;
-    S.ery[ex_me] = ery;
-    S.eryp[ex_me] = ery_prev;
-    if (extra_corner) S.erz[T::e(xci, xcj)] = erz_extra;
+    if constexpr (!HY) {
+      S.zex[ex_me] = fz.fb2;
+      S.zey[ex_me] = -fz.fb1;
+      S.zmass[ex_me] = fz.cons[0];
+      S.erz[ex_me] = erz;
+      S.erx[ex_me] = erx;
+      S.erxp[ex_me] = erx_prev;
+      S.ery[ex_me] = ery;
+      S.eryp[ex_me] = ery_prev;
+      if (extra_corner) S.erz[T::e(xci, xcj)] = erz_extra;
+    }
     __syncthreads();  // plane-m primitives no longer read
     // ---------------- B: the next primitive plane
     {
       const int iw = T::w(ci, cj);
-      S.w[0][iw] = w1.rho; S.w[1][iw] = w1.vx; S.w[2][iw] = w1.vy; S.w[3][iw] = w1.vz;
-      S.w[4][iw] = w1.bx; S.w[5][iw] = w1.by; S.w[6][iw] = w1.bz; S.w[7][iw] = w1.p;
+      put_cell<HY>(S, iw, w1);
     }
     if (has_extra) {
       const int jw = T::w(xci, xcj);
-      S.w[0][jw] = wx.rho; S.w[1][jw] = wx.vx; S.w[2][jw] = wx.vy; S.w[3][jw] = wx.vz;
-      S.w[4][jw] = wx.bx; S.w[5][jw] = wx.by; S.w[6][jw] = wx.bz; S.w[7][jw] = wx.p;
+      put_cell<HY>(S, jw, wx);
     }
     __syncthreads();
 
     // ---------------- C: corner EMFs, cell update of plane m-1
     R ez_new = 0, ex_new = 0, ey_new = 0;
+    if constexpr (!HY) {
     if (do_ez && m >= z0 && m < z1) {
       const int e_s = T::e(ci, cj - 1), e_w = T::e(ci - 1, cj), e_sw = T::e(ci - 1, cj - 1);
       ez_new = corner_emf<EMF>(S.xez[ex_me], S.xez[e_s], S.yez[ex_me], S.yez[e_w], S.erz[e_sw],
@@ -572,6 +624,7 @@ stage_kernel(BatchArgs ba) {
                             ery, fz.cons[0], S.zmass[e_w], xmass_now, xmass_prev);
       }
     }
+    }  // !HY
     // partial update of cell m (x then y), kept for the next iteration
     R part_new[5];
     R cxy_new = 0;
@@ -605,7 +658,10 @@ stage_kernel(BatchArgs ba) {
         }
 #pragma unroll
         for (int q = 0; q < 5; ++q) gst(a.dst[q], o, un[q]);
-        if constexpr (CT == CT_FACE) {
+        if constexpr (HY) {
+          gst(a.dst[5], o, R(0));
+          gst(a.dst[6], o, R(0));
+        } else if constexpr (CT == CT_FACE) {
           const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
           R bxn = (gld(a.src[5], o) - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
           R byn = (gld(a.src[6], o) - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
@@ -621,14 +677,18 @@ stage_kernel(BatchArgs ba) {
     __syncthreads();  // reads of corner-EMF buffers of plane m-1 done
 
     // ---------------- D: publish corner EMFs; E: B_z on face m-1/2
-    if (do_ez) S.ez[ex_me] = ez_new;
-    if (do_ex) S.ex[ex_me] = ex_new;
-    if (do_ey) S.ey[ex_me] = ey_new;
-    __syncthreads();
+    if constexpr (!HY) {
+      if (do_ez) S.ez[ex_me] = ez_new;
+      if (do_ex) S.ex[ex_me] = ex_new;
+      if (do_ey) S.ey[ex_me] = ey_new;
+      __syncthreads();
+    }
     if constexpr (MODE != MODE_MEASURE) {
       if (real && m >= z0 && m < z1) {
         const long long o = (long long)km * plane + col;
-        if constexpr (CT == CT_FACE) {
+        if constexpr (HY) {
+          gst(a.dst[7], o, R(0));
+        } else if constexpr (CT == CT_FACE) {
           const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
           R bzn = (bz_m - tau_x * (S.ey[e_e] - ey_new)) + tau_y * (S.ex[e_n] - ex_new);
           if constexpr (MODE == MODE_COMBINE) bzn = a.w * bzn + a.w0 * gld<R>(a.dst[7], o + a.boff);
@@ -685,7 +745,7 @@ stage_kernel(BatchArgs ba) {
 template <typename R, int SOLVER, int RECON, int EMF, int CT, int MODE, int TX, int TY>
 static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) {
   using T = Tile<TX, TY>;
-  const size_t lds = sizeof(SmemAll<R, TX, TY>);
+  const size_t lds = sizeof(SmemAll<R, TX, TY, SOLVER == SOLVER_HLLC>);
   auto fn = stage_kernel<R, SOLVER, RECON, EMF, CT, MODE, TX, TY>;
   if (prepare)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
