@@ -27,7 +27,7 @@ FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
 HLLD, HLL, HLLC = 0, 1, 2
 RK2, EULER, RK3 = 0, 1, 2
 EMF_EC, EMF_E0, EMF_ARITH = 0, 1, 2
-PLM, LIMO3 = 0, 1
+PLM, LIMO3, PPM = 0, 1, 2
 OK, ERR_INVALID_ARG, ERR_NOMEM, ERR_NONPHYSICAL = 0, -1, -2, -4
 
 # -ffp-contract=off: no fused multiply-add, every expression rounds as written.
@@ -85,6 +85,7 @@ def lib():
         L.orc_limo3_phi.argtypes = [C.c_double]
         L.orc_limo3_phi.restype = C.c_double
         L.orc_recon.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_ppm_faces.argtypes = [dp, dp, dp]
         for fn in (L.orc_fast_speed, L.orc_slow_speed):
             fn.argtypes = [C.c_double] * 6
             fn.restype = C.c_double
@@ -203,6 +204,15 @@ def recon(kind: int, q0: float, q1: float, q2: float):
     """(lower, upper) face values of cell q1 between q0 and q2."""
     lo, hi = C.c_double(), C.c_double()
     lib().orc_recon(kind, q0, q1, q2, C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def ppm_faces(a) -> tuple:
+    """PPM (lower, upper) face values of cell a[2] from the five cells a[0..4]."""
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    assert arr.shape == (5,)
+    lo, hi = C.c_double(), C.c_double()
+    lib().orc_ppm_faces(_dptr(arr), C.byref(lo), C.byref(hi))
     return lo.value, hi.value
 
 

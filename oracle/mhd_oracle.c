@@ -12,8 +12,8 @@
  *   S1  conserved -> primitive variables; cell-centred B is the mean of the two
  *       faces (the face-to-cell rule of Sec. 3.3 output).
  *   S2  piecewise-linear reconstruction of (rho, v, B_t, p) with the van Leer
- *       limiter, or the LimO3 third-order reconstruction (Sec. 2.3); B_n on a
- *       face is the staggered face value (Sec. 2.4).
+ *       limiter, or the LimO3 third-order or PPM reconstructions (Sec. 2.3); B_n
+ *       on a face is the staggered face value (Sec. 2.4).
  *   S3  HLL (Einfeldt et al. 1991) or HLLD (Miyoshi & Kusano 2005) flux on every
  *       x, y, z face, or HLLC (Toro et al. 1994) for B = 0 problems; pressure is
  *       inside the momentum flux (Sec. 2.3).  The same solve yields c_max for
@@ -81,13 +81,18 @@ static int check_params(const orc_params* p) {
     return ORC_ERR_INVALID_ARG;
   if (p->emf != ORC_EMF_EC && p->emf != ORC_EMF_E0 && p->emf != ORC_EMF_ARITH)
     return ORC_ERR_INVALID_ARG;
-  if (p->recon != ORC_PLM && p->recon != ORC_LIMO3) return ORC_ERR_INVALID_ARG;
+  if (p->recon != ORC_PLM && p->recon != ORC_LIMO3 && p->recon != ORC_PPM)
+    return ORC_ERR_INVALID_ARG;
   return ORC_OK;
 }
 
 /* periodic neighbour indices (Sec. 2.6 grid, periodic in every direction) */
 static inline int up(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 static inline int dn(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+static inline int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
 static inline long at(const grid_t* g, int i, int j, int k) {
   return ((long)k * g->ny + j) * g->nx + i;
 }
@@ -135,6 +140,81 @@ void orc_recon(int recon, double q0, double q1, double q2, double* lo, double* h
   *lo = recon_lo(recon, q0, q1, q2);
   *hi = recon_hi(recon, q0, q1, q2);
 }
+
+/* S2 with PPM (Sec. 2.3: Colella & Woodward 1984 with the extremum-preserving
+ * limiter of Colella & Sekora 2008), on the five cells a[0..4] = j-2 .. j+2
+ * around cell j; *lo and *hi receive the values at its lower and upper face.
+ *  1. fourth-order interface value a_{j+1/2} = 7/12 (a_j + a_{j+1})
+ *     - 1/12 (a_{j-1} + a_{j+2});
+ *  2. where it is not between a_j and a_{j+1}: D2 = 3 (a_j - 2 a_{j+1/2} +
+ *     a_{j+1}), D2L = a_{j-1} - 2 a_j + a_{j+1}, D2R = a_j - 2 a_{j+1} + a_{j+2};
+ *     D2lim = sign(D2) min(C |D2L|, C |D2R|, |D2|) if the three share a sign,
+ *     else 0; a_{j+1/2} = (a_j + a_{j+1})/2 - D2lim/6 (the factor for which an
+ *     unclipped D2lim = D2 returns the fourth-order value unchanged);
+ *  3. in cell j, at an extremum ((a+ - a_j)(a_j - a-) <= 0 or (a_{j+1} - a_j)
+ *     (a_j - a_{j-1}) <= 0): D2 = -2 (6 a_j - 3 (a- + a+)), D2C = a_{j-1} -
+ *     2 a_j + a_{j+1}, D2L = a_{j-2} - 2 a_{j-1} + a_j, D2R = a_j - 2 a_{j+1} +
+ *     a_{j+2}; D2lim = sign(D2) min(C |D2L|, C |D2R|, C |D2C|, |D2|) if all four
+ *     share a sign, else 0; a+- = a_j + (a+- - a_j) D2lim / D2 (a_j if D2 = 0);
+ *     elsewhere the overshoot checks of Colella & Woodward: if |a+ - a_j| >=
+ *     2 |a- - a_j| then a+ = a_j - 2 (a- - a_j), and symmetrically for a-;
+ *  C = 1.25. */
+static double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+static double ppm_interface(double am, double a0, double a1, double a2) {
+  const double C = 1.25;
+  double ai = (7.0 / 12.0) * (a0 + a1) - (1.0 / 12.0) * (am + a2);
+  if ((ai - a0) * (a1 - ai) < 0.0) {
+    double d2 = 3.0 * ((a0 - 2.0 * ai) + a1);
+    double d2l = (am - 2.0 * a0) + a1;
+    double d2r = (a0 - 2.0 * a1) + a2;
+    double lim = 0.0;
+    if (sgn(d2) == sgn(d2l) && sgn(d2) == sgn(d2r)) {
+      double m = C * fabs(d2l);
+      m = C * fabs(d2r) < m ? C * fabs(d2r) : m;
+      m = fabs(d2) < m ? fabs(d2) : m;
+      lim = sgn(d2) * m;
+    }
+    ai = 0.5 * (a0 + a1) - lim / 6.0;
+  }
+  return ai;
+}
+
+static void ppm_faces(const double* a, double* lo, double* hi) {
+  const double C = 1.25;
+  double aj = a[2];
+  double am = ppm_interface(a[0], a[1], a[2], a[3]);
+  double ap = ppm_interface(a[1], a[2], a[3], a[4]);
+  if ((ap - aj) * (aj - am) <= 0.0 || (a[3] - aj) * (aj - a[1]) <= 0.0) {
+    double d2 = -2.0 * (6.0 * aj - 3.0 * (am + ap));
+    double d2c = (a[1] - 2.0 * aj) + a[3];
+    double d2l = (a[0] - 2.0 * a[1]) + aj;
+    double d2r = (aj - 2.0 * a[3]) + a[4];
+    double lim = 0.0;
+    if (sgn(d2) == sgn(d2c) && sgn(d2) == sgn(d2l) && sgn(d2) == sgn(d2r)) {
+      double m = C * fabs(d2l);
+      m = C * fabs(d2r) < m ? C * fabs(d2r) : m;
+      m = C * fabs(d2c) < m ? C * fabs(d2c) : m;
+      m = fabs(d2) < m ? fabs(d2) : m;
+      lim = sgn(d2) * m;
+    }
+    if (d2 != 0.0) {
+      double r = lim / d2;
+      am = aj + (am - aj) * r;
+      ap = aj + (ap - aj) * r;
+    } else {
+      am = aj;
+      ap = aj;
+    }
+  } else {
+    if (fabs(ap - aj) >= 2.0 * fabs(am - aj)) ap = aj - 2.0 * (am - aj);
+    if (fabs(am - aj) >= 2.0 * fabs(ap - aj)) am = aj - 2.0 * (ap - aj);
+  }
+  *lo = am;
+  *hi = ap;
+}
+
+void orc_ppm_faces(const double a[5], double* lo, double* hi) { ppm_faces(a, lo, hi); }
 
 /* Fast and slow magnetosonic speeds from a^2 = gamma p / rho, total and normal
  * Alfven speeds (standard ideal-MHD wave speeds). */
@@ -516,35 +596,31 @@ static void faces(const grid_t* g, const orc_state* s, work_t* w, int d) {
   for (int k = 0; k < g->nz; ++k)
     for (int j = 0; j < g->ny; ++j)
       for (int i = 0; i < g->nx; ++i) {
-        /* the four cells c-2, c-1, c, c+1 along d */
-        long c[4];
-        if (d == 0) {
-          int im1 = dn(i, g->nx);
-          c[0] = at(g, dn(im1, g->nx), j, k);
-          c[1] = at(g, im1, j, k);
-          c[2] = at(g, i, j, k);
-          c[3] = at(g, up(i, g->nx), j, k);
-        } else if (d == 1) {
-          int jm1 = dn(j, g->ny);
-          c[0] = at(g, i, dn(jm1, g->ny), k);
-          c[1] = at(g, i, jm1, k);
-          c[2] = at(g, i, j, k);
-          c[3] = at(g, i, up(j, g->ny), k);
-        } else {
-          int km1 = dn(k, g->nz);
-          c[0] = at(g, i, j, dn(km1, g->nz));
-          c[1] = at(g, i, j, km1);
-          c[2] = at(g, i, j, k);
-          c[3] = at(g, i, j, up(k, g->nz));
+        /* the six cells c-3 .. c+2 along d (face c-1/2 lies between c-1 and c) */
+        long c[6];
+        for (int q = 0; q < 6; ++q) {
+          if (d == 0)
+            c[q] = at(g, wrap(i - 3 + q, g->nx), j, k);
+          else if (d == 1)
+            c[q] = at(g, i, wrap(j - 3 + q, g->ny), k);
+          else
+            c[q] = at(g, i, j, wrap(k - 3 + q, g->nz));
         }
         double wl[7], wr[7], fl[7], cmax;
         for (int v = 0; v < 7; ++v) {
           const double* q = w->w[frame[d][v]];
-          double q0 = q[c[0]], q1 = q[c[1]], q2 = q[c[2]], q3 = q[c[3]];
-          wl[v] = recon_hi(g->recon, q0, q1, q2); /* upper face of cell c-1 */
-          wr[v] = recon_lo(g->recon, q1, q2, q3); /* lower face of cell c */
+          double a[6];
+          for (int u = 0; u < 6; ++u) a[u] = q[c[u]];
+          if (g->recon == ORC_PPM) {
+            double unused;
+            ppm_faces(a, &unused, &wl[v]);     /* upper face of cell c-1 */
+            ppm_faces(a + 1, &wr[v], &unused); /* lower face of cell c */
+          } else {
+            wl[v] = recon_hi(g->recon, a[1], a[2], a[3]); /* upper face of cell c-1 */
+            wr[v] = recon_lo(g->recon, a[2], a[3], a[4]); /* lower face of cell c */
+          }
         }
-        long o = c[2];
+        long o = c[3];
         riemann(g->riemann, g->gamma, g->igm1, wl, wr, bnarr[o], fl, &cmax);
         w->f[d][F_RHO][o] = fl[0];
         w->f[d][mom_of[d][0]][o] = fl[1];

@@ -23,8 +23,8 @@ enum { ORC_HLLD = 0, ORC_HLL = 1, ORC_HLLC = 2 }; /* HLLC: hydrodynamics, B = 0 
 enum { ORC_RK2 = 0, ORC_EULER = 1, ORC_RK3 = 2 };
 /* corner-EMF schemes of Sec. 2.4: E^c (default), E^0, arithmetic average */
 enum { ORC_EMF_EC = 0, ORC_EMF_E0 = 1, ORC_EMF_ARITH = 2 };
-/* reconstructions of Sec. 2.3: van Leer PLM (default), LimO3 */
-enum { ORC_PLM = 0, ORC_LIMO3 = 1 };
+/* reconstructions of Sec. 2.3: van Leer PLM (default), LimO3, PPM */
+enum { ORC_PLM = 0, ORC_LIMO3 = 1, ORC_PPM = 2 };
 
 enum {
   ORC_OK = 0,
@@ -41,7 +41,7 @@ typedef struct {
   int riemann;         /* ORC_HLLD, ORC_HLL or ORC_HLLC */
   int integrator;      /* ORC_RK2, ORC_EULER or ORC_RK3 (Tab. weights) */
   int emf;             /* ORC_EMF_EC, ORC_EMF_E0 or ORC_EMF_ARITH */
-  int recon;           /* ORC_PLM or ORC_LIMO3 */
+  int recon;           /* ORC_PLM, ORC_LIMO3 or ORC_PPM */
 } orc_params;
 
 typedef struct {
@@ -96,6 +96,8 @@ double orc_limo3_phi(double theta);
 /* Face values of a cell q1 between neighbours q0 (below) and q2 (above):
  * *lo at its lower face, *hi at its upper face, for ORC_PLM or ORC_LIMO3. */
 void orc_recon(int recon, double q0, double q1, double q2, double* lo, double* hi);
+/* PPM face values (*lo, *hi) of cell a[2] from the five cells a[0..4]. */
+void orc_ppm_faces(const double a[5], double* lo, double* hi);
 
 /* Fast magnetosonic speed of a state (rho, p, Bn, Bt1, Bt2). */
 double orc_fast_speed(double gamma, double rho, double p, double bn, double bt1, double bt2);

@@ -37,6 +37,7 @@ static inline bool operator<(CD a, CD b) { return a.v < b.v; }
 static inline bool operator>=(CD a, CD b) { return a.v >= b.v; }
 static inline bool operator<=(CD a, CD b) { return a.v <= b.v; }
 static inline bool operator==(CD a, CD b) { return a.v == b.v; }
+static inline bool operator!=(CD a, CD b) { return a.v != b.v; }
 static inline CD sqrt_c(CD a) { ++g_sqrt; return CD(std::sqrt(a.v)); }
 static inline CD fabs_c(CD a) { return CD(std::fabs(a.v)); }
 static inline bool isfinite_c(CD a) { return std::isfinite(a.v); }
