@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -130,7 +131,37 @@ def cpu_baseline(state):
     el = time.perf_counter() - t0
     return {"value": round(2 * N ** 3 / el, 1), "unit": "cell-updates/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"2 RK2 cycles of the same 256^3 FP64 input ({el:.1f} s, OpenMP)"}
+            "sample": f"2 RK2 cycles of the same 256^3 FP64 input ({el:.1f} s, OpenMP)",
+            "error_vs_oracle": errors_vs_oracle(state, s)}
+
+
+def errors_vs_oracle(state, ref):
+    """Errors of the GPU results after the same 2 cycles against the oracle's:
+    FP64 (expected bit-identical) and FP32 (input rounded to FP32 by the
+    library), per quantity as max|gpu - oracle| / max|oracle| and as the ratio
+    of L2 norms."""
+    from paper_2304_13746_amd.box import MHDBox
+
+    groups = {"rho": ("rho",), "momentum": ("mx", "my", "mz"), "energy": ("en",),
+              "field": ("bx", "by", "bz")}
+    out = {}
+    for prec in ("fp64", "fp32"):
+        box = MHDBox(N, N, N, precision=prec)
+        box.set_state(state)
+        box.step(2)
+        g, _, _, _ = box.get_state_numpy()
+        box.close()
+        e = {}
+        for name, fs in groups.items():
+            den = max(float(np.max(np.abs(ref[f]))) for f in fs)
+            num = max(float(np.max(np.abs(g[f] - ref[f]))) for f in fs)
+            l2 = math.sqrt(sum(float(np.sum((g[f] - ref[f]) ** 2)) for f in fs) /
+                           sum(float(np.sum(ref[f] ** 2)) for f in fs))
+            e[name] = {"max_rel": float(f"{num / den:.3e}"), "l2_rel": float(f"{l2:.3e}")}
+        if prec == "fp64":
+            e["bit_identical"] = all(np.array_equal(g[f], ref[f]) for f in ref)
+        out[prec] = e
+    return out
 
 
 def batched_c3(nbox: int = 64, steps: int = 20):
@@ -303,12 +334,13 @@ def main():
                         "roofline": f["roofline"]}
     if not args.no_next:
         # widened scheme options on the same input: the third-order Runge-Kutta
-        # cycle (three stage launches per cycle), LimO3 reconstruction with RK3,
-        # and the E^0 / arithmetic corner EMFs (two launches per cycle)
+        # cycle (three stage launches per cycle), LimO3 and PPM reconstructions
+        # with RK3, and the E^0 / arithmetic corner EMFs (two launches per cycle)
         nxt = {}
         k = min(args.steps, 20)
         for name, integ, emf, recon, nst in (("rk3", "rk3", "ec", "plm", 3),
                                              ("limo3_rk3", "rk3", "ec", "limo3", 3),
+                                             ("ppm_rk3", "rk3", "ec", "ppm", 3),
                                              ("emf_e0", "rk2", "e0", "plm", 2),
                                              ("emf_arith", "rk2", "arith", "plm", 2)):
             for prec in precs:

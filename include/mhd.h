@@ -6,8 +6,8 @@
  * energy with viscosity, gravity, resistivity and conduction set to zero) with the
  * Godunov finite-volume cycle of Sec. 2.2-2.7:
  *   conserved U = (rho, rho v, E) at cell centres and B on cell faces (Sec. 2.2,
- *   2.4); per stage: primitive reconstruction with the van Leer limiter or LimO3
- *   (Sec. 2.3),
+ *   2.4); per stage: primitive reconstruction with the van Leer limiter, LimO3 or
+ *   PPM (Sec. 2.3),
  *   an HLLD or HLL Riemann solve on every x, y and z face (Sec. 2.3), corner EMFs
  *   by the upwind-by-contact E^c scheme or its E^0 and arithmetic variants
  *   (Sec. 2.4), the flux-divergence update of U
@@ -59,9 +59,12 @@ typedef enum { MHD_HLLD = 0, MHD_HLL = 1, MHD_HLLC = 2 } mhd_riemann;
 /* Corner-EMF schemes of Sec. 2.4 (Gardiner & Stone 2005): E^c (default), E^0
  * and the arithmetic mean of the four face EMFs. */
 typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2 } mhd_emf;
-/* Reconstructions of Sec. 2.3: van Leer PLM (default) and the compact
- * third-order LimO3 limiter (Cada & Torrilhon 2009), both on the primitives. */
-typedef enum { MHD_PLM = 0, MHD_LIMO3 = 1 } mhd_recon;
+/* Reconstructions of Sec. 2.3, all on the primitives: van Leer PLM (default),
+ * the compact third-order LimO3 limiter (Cada & Torrilhon 2009), and PPM
+ * (Colella & Woodward 1984) with the extremum-preserving limiter of Colella &
+ * Sekora (2008).  PPM reads three cells each way and is built with
+ * MHD_CT_FACE and, for HLLD/HLL, MHD_EMF_EC (else MHD_ERR_UNSUPPORTED). */
+typedef enum { MHD_PLM = 0, MHD_LIMO3 = 1, MHD_PPM = 2 } mhd_recon;
 /* Constrained transport (Sec. 2.4): the face field updated by the discrete
  * Stokes theorem, or carried by an edge vector potential A (eqs. ind_vec:
  * dA/dt = -E, B = b0 + curl A, b0 the uniform mean field); the potential form

@@ -35,6 +35,13 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double dvd(double a, double b) { return a / b; }
 __device__ __forceinline__ float dvd(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// Quotient with IEEE division in both precisions, for limiter ratios whose
+// divisor can be arbitrarily small (differences of nearly uniform data): the FP32
+// reciprocal overflows for subnormal divisors and 0 * inf is NaN, while a true
+// quotient by a nonzero divisor is never NaN.  (Van Leer's ratio needs no such
+// care: its numerator dm dp > 0 bounds the divisor away from the subnormals.)
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a / b; }
 __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
 
@@ -46,13 +53,13 @@ __device__ __forceinline__ R van_leer(R dm, R dp) {
   return s > R(0) ? dvd(R(2) * s, dp + dm) : R(0);
 }
 
-// Reconstructions of Sec. 2.3: van Leer PLM, or the compact third-order LimO3
-// limiter of Cada & Torrilhon (2009), applied everywhere (its smooth-extremum
-// switch needs a problem length scale and is not used):
+// Reconstructions of Sec. 2.3: van Leer PLM, PPM (below), or the compact
+// third-order LimO3 limiter of Cada & Torrilhon (2009), applied everywhere (its
+// smooth-extremum switch needs a problem length scale and is not used):
 //   upper face q + phi(dm/dp) dp / 2, lower face q - phi(dp/dm) dm / 2,
 //   phi(t) = max(0, min(p3, max(-t/2, min(2t, p3, 1.6)))), p3 = (2 + t)/3;
 // a zero difference leaves the face at the cell value.
-enum { RECON_PLM = 0, RECON_LIMO3 = 1 };
+enum { RECON_PLM = 0, RECON_LIMO3 = 1, RECON_PPM = 2 };
 
 template <typename R>
 __device__ __forceinline__ R limo3_phi(R th) {
@@ -69,7 +76,7 @@ template <int RECON, typename R>
 __device__ __forceinline__ R recon_hi(R q0, R q1, R q2) {
   const R dm = q1 - q0, dp = q2 - q1;
   if constexpr (RECON == RECON_LIMO3)
-    return dp == R(0) ? q1 : q1 + (R(0.5) * limo3_phi(dvd(dm, dp))) * dp;
+    return dp == R(0) ? q1 : q1 + (R(0.5) * limo3_phi(qdiv(dm, dp))) * dp;
   else
     return q1 + R(0.5) * van_leer(dm, dp);
 }
@@ -77,10 +84,76 @@ template <int RECON, typename R>
 __device__ __forceinline__ R recon_lo(R q0, R q1, R q2) {
   const R dm = q1 - q0, dp = q2 - q1;
   if constexpr (RECON == RECON_LIMO3)
-    return dm == R(0) ? q1 : q1 - (R(0.5) * limo3_phi(dvd(dp, dm))) * dm;
+    return dm == R(0) ? q1 : q1 - (R(0.5) * limo3_phi(qdiv(dp, dm))) * dm;
   else
     return q1 - R(0.5) * van_leer(dm, dp);
 }
+// PPM (Colella & Woodward 1984) with the extremum-preserving limiter of
+// Colella & Sekora (2008), C = 1.25: a fourth-order interface value, limited
+// where it leaves the interval of its two cells, then the cell's two face
+// values, limited at extrema by the smallest consistent second difference and
+// elsewhere by the Colella-Woodward overshoot checks.
+template <typename R>
+__device__ __forceinline__ R sgn(R x) {
+  return x > R(0) ? R(1) : (x < R(0) ? R(-1) : R(0));
+}
+
+template <typename R>
+__device__ __forceinline__ R ppm_interface(R am, R a0, R a1, R a2) {
+  const R C = R(1.25);
+  R ai = R(7.0 / 12.0) * (a0 + a1) - R(1.0 / 12.0) * (am + a2);
+  if ((ai - a0) * (a1 - ai) < R(0)) {
+    const R d2 = R(3) * ((a0 - R(2) * ai) + a1);
+    const R d2l = (am - R(2) * a0) + a1;
+    const R d2r = (a0 - R(2) * a1) + a2;
+    R lim = R(0);
+    if (sgn(d2) == sgn(d2l) && sgn(d2) == sgn(d2r)) {
+      R m = C * dabs(d2l);
+      m = C * dabs(d2r) < m ? C * dabs(d2r) : m;
+      m = dabs(d2) < m ? dabs(d2) : m;
+      lim = sgn(d2) * m;
+    }
+    ai = R(0.5) * (a0 + a1) - dvd(lim, R(6));
+  }
+  return ai;
+}
+
+// face values of cell a2 from the five cells a0 .. a4
+template <typename R>
+__device__ __forceinline__ void ppm_faces(R a0, R a1, R a2, R a3, R a4, R& lo, R& hi) {
+  const R C = R(1.25);
+  const R aj = a2;
+  R am = ppm_interface(a0, a1, a2, a3);
+  R ap = ppm_interface(a1, a2, a3, a4);
+  if ((ap - aj) * (aj - am) <= R(0) || (a3 - aj) * (aj - a1) <= R(0)) {
+    const R d2 = R(-2) * (R(6) * aj - R(3) * (am + ap));
+    const R d2c = (a1 - R(2) * aj) + a3;
+    const R d2l = (a0 - R(2) * a1) + aj;
+    const R d2r = (aj - R(2) * a3) + a4;
+    R lim = R(0);
+    if (sgn(d2) == sgn(d2c) && sgn(d2) == sgn(d2l) && sgn(d2) == sgn(d2r)) {
+      R m = C * dabs(d2l);
+      m = C * dabs(d2r) < m ? C * dabs(d2r) : m;
+      m = C * dabs(d2c) < m ? C * dabs(d2c) : m;
+      m = dabs(d2) < m ? dabs(d2) : m;
+      lim = sgn(d2) * m;
+    }
+    if (d2 != R(0)) {
+      const R r = qdiv(lim, d2);
+      am = aj + (am - aj) * r;
+      ap = aj + (ap - aj) * r;
+    } else {
+      am = aj;
+      ap = aj;
+    }
+  } else {
+    if (dabs(ap - aj) >= R(2) * dabs(am - aj)) ap = aj - R(2) * (am - aj);
+    if (dabs(am - aj) >= R(2) * dabs(ap - aj)) am = aj - R(2) * (ap - aj);
+  }
+  lo = am;
+  hi = ap;
+}
+
 // both faces of one cell (PLM shares its one limited slope)
 template <int RECON, typename R>
 __device__ __forceinline__ void recon_pair(R q0, R q1, R q2, R& lo, R& hi) {

@@ -163,6 +163,22 @@ __device__ __forceinline__ Prim<R> as_prim(const R* q) {
   return w;
 }
 
+// The two states of the face between cells q[NS/2 - 1] and q[NS/2] of a line of
+// NS cells (NS = 4 for PLM and LimO3, 6 for PPM), variable v.
+template <int RECON, int NS, typename R>
+__device__ __forceinline__ void face_states(const R (&q)[NS][7], int v, R& ql, R& qr) {
+  if constexpr (RECON == RECON_PPM) {
+    R lo, hi;
+    ppm_faces(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v], lo, hi);
+    ql = hi;  // upper face of the cell below the face
+    ppm_faces(q[1][v], q[2][v], q[3][v], q[4][v], q[5][v], lo, hi);
+    qr = lo;  // lower face of the cell above it
+  } else {
+    ql = recon_hi<RECON>(q[0][v], q[1][v], q[2][v]);
+    qr = recon_lo<RECON>(q[1][v], q[2][v], q[3][v]);
+  }
+}
+
 // Per-face result kept by the owning thread.
 template <typename R>
 struct Face {
@@ -182,14 +198,17 @@ __device__ __forceinline__ void solve_face(const StageArgs<R>& a, const R* ql, c
 }
 
 // Tile geometry: TX x TY interior, threads own interior columns then the ring.
-template <int TX, int TY>
+// H is the halo of the primitive plane: 2 cells for PLM and LimO3, 3 for PPM.
+template <int TX, int TY, int H = 2>
 struct Tile {
   static constexpr int NT = TX * TY + 2 * (TX + TY);  // threads per block
   static constexpr int EP = TX + 2, EQ = TY + 2;      // extended column grid
   static constexpr int NE = EP * EQ;
-  static constexpr int WP = TX + 4, WQ = TY + 4;      // primitive plane with 2-halo
+  static constexpr int WP = TX + 2 * H, WQ = TY + 2 * H;  // primitive plane with its halo
   static constexpr int NW = WP * WQ;
-  static constexpr int NX_EXTRA = 2 * (TX + TY) + 10;  // halo primitives no thread owns
+  // halo primitives no thread owns
+  static constexpr int NX_EXTRA = H == 2 ? 2 * (TX + TY) + 10 : 4 + 4 * (TY + 2) + 4 * (TX + 2);
+  static_assert(NX_EXTRA <= NT, "one halo item per thread at most");
   __device__ static void column(int t, int& ci, int& cj) {
     if (t < TX * TY) {
       ci = t % TX;
@@ -205,8 +224,31 @@ struct Tile {
     r -= TX;
     ci = r; cj = TY;
   }
-  // halo primitive items: second ring and the four corners of the first ring
+  // halo primitive items: second ring and the four corners of the first ring;
+  // with a 3-cell halo the four corners, then the columns -3, -2, TX+1, TX+2
+  // over rows -1 .. TY and the rows -3, -2, TY+1, TY+2 over columns -1 .. TX
+  // (the cells the x- and y-faces of the tile and its ring read)
   __device__ static void extra(int t, int& ci, int& cj) {
+    if constexpr (H == 3) {
+      int r = t;
+      if (r < 4) {
+        ci = (r & 1) ? TX : -1;
+        cj = (r & 2) ? TY : -1;
+        return;
+      }
+      r -= 4;
+      if (r < 4 * (TY + 2)) {
+        const int c = r / (TY + 2);
+        ci = c == 0 ? -3 : (c == 1 ? -2 : (c == 2 ? TX + 1 : TX + 2));
+        cj = r % (TY + 2) - 1;
+        return;
+      }
+      r -= 4 * (TY + 2);
+      const int c = r / (TX + 2);
+      cj = c == 0 ? -3 : (c == 1 ? -2 : (c == 2 ? TY + 1 : TY + 2));
+      ci = r % (TX + 2) - 1;
+      return;
+    }
     int r = t;
     if (r < TY + 2) { ci = -2; cj = r - 1; return; }
     r -= TY + 2;
@@ -220,13 +262,13 @@ struct Tile {
     cj = (r & 2) ? TY : -1;
   }
   __device__ static int e(int ci, int cj) { return (cj + 1) * EP + (ci + 1); }
-  __device__ static int w(int ci, int cj) { return (cj + 2) * WP + (ci + 2); }
+  __device__ static int w(int ci, int cj) { return (cj + H) * WP + (ci + H); }
 };
 
 // LDS layout (units of R): primitive plane, per-column exports, corner EMFs.
-template <typename R, int TX, int TY>
+template <typename R, int TX, int TY, int H>
 struct Smem {
-  using T = Tile<TX, TY>;
+  using T = Tile<TX, TY, H>;
   R w[8][T::NW];
   R xcons[5][T::NE], xez[T::NE], xmass[T::NE], xcmax[T::NE];
   R ycons[5][T::NE], yez[T::NE], ymass[T::NE], ycmax[T::NE];
@@ -241,24 +283,24 @@ struct Smem {
 template <typename R, int TX, int TY>
 struct Carry {
   static constexpr bool in_lds = sizeof(R) == 8 && TX == 16;
-  static constexpr int NT = Tile<TX, TY>::NT;
+  static constexpr int NT = Tile<TX, TY, 2>::NT;
   static constexpr int N = in_lds ? NT : 1;
   R part[5][N], fzp[5][N];
 };
 
 // The hydrodynamic layout (HLLC, B = 0): primitives rho, v, p and the flux
 // exports of the divergence and the CFL condition only.
-template <typename R, int TX, int TY>
+template <typename R, int TX, int TY, int H>
 struct SmemHydro {
-  using T = Tile<TX, TY>;
+  using T = Tile<TX, TY, H>;
   R w[5][T::NW];
   R xcons[5][T::NE], xcmax[T::NE];
   R ycons[5][T::NE], ycmax[T::NE];
 };
 
-template <typename R, int TX, int TY, bool HY>
+template <typename R, int TX, int TY, bool HY, int H>
 struct SmemAll {
-  std::conditional_t<HY, SmemHydro<R, TX, TY>, Smem<R, TX, TY>> s;
+  std::conditional_t<HY, SmemHydro<R, TX, TY, H>, Smem<R, TX, TY, H>> s;
   Carry<R, TX, TY> c;
 };
 
@@ -293,22 +335,29 @@ __device__ __forceinline__ void get_cell(const SM& S, int iw, Cell<R>& c) {
 #define MHD_WAVES_F64 2
 #endif
 // The hydrodynamic path (no field, no EMFs) fits one more wave per SIMD.
-template <typename R, bool HY>
+// FP64 PPM holds two more planes of its z-window in registers: the hydrodynamic
+// path keeps the MHD path's two waves, and the MHD path, whose wider LDS halo
+// leaves room for one block per CU only, takes the whole register file.
+template <typename R, bool HY, bool PPM>
 struct Occupancy {
-  static constexpr int waves = (sizeof(R) == 4 ? MHD_WAVES_F32 : MHD_WAVES_F64) + (HY ? 1 : 0);
+  static constexpr int waves = sizeof(R) == 4 ? MHD_WAVES_F32 + (HY ? 1 : 0)
+                               : PPM          ? (HY ? MHD_WAVES_F64 : 1)
+                                              : MHD_WAVES_F64 + (HY ? 1 : 0);
 };
 
 template <typename R, int SOLVER, int RECON, int EMF, int CT, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY + 2 * (TX + TY))
-__attribute__((amdgpu_waves_per_eu(Occupancy<R, SOLVER == SOLVER_HLLC>::waves)))
+__attribute__((amdgpu_waves_per_eu(Occupancy<R, SOLVER == SOLVER_HLLC, RECON == RECON_PPM>::waves)))
 stage_kernel(BatchArgs ba) {
-  using T = Tile<TX, TY>;
+  constexpr int H = RECON == RECON_PPM ? 3 : 2;
+  constexpr int NS = 2 * H;  // cells a face's two states read along its direction
+  using T = Tile<TX, TY, H>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // HLLC is the hydrodynamic path: no field is read, no EMF is formed, the face
   // field is written as zero, and the ring columns solve only the x- and
   // y-faces the tile's own cells need
   constexpr bool HY = SOLVER == SOLVER_HLLC;
-  using SA_t = SmemAll<R, TX, TY, HY>;
+  using SA_t = SmemAll<R, TX, TY, HY, H>;
   SA_t& SA = *reinterpret_cast<SA_t*>(smem_raw);
   auto& S = SA.s;
   constexpr bool CL = Carry<R, TX, TY>::in_lds;
@@ -394,6 +443,11 @@ stage_kernel(BatchArgs ba) {
   // cell m-1
   R zm1[7];
   R top7[7];
+  // PPM reaches two planes each way: the z-frame of plane m-2 and the
+  // primitives of plane m+1 (read one iteration ahead) join the window
+  constexpr bool PPM = RECON == RECON_PPM;
+  R zm2[PPM ? 7 : 1];
+  Cell<R> wn;
   // U - tau_x dFx - tau_y dFy of cell m-1 and the z-flux at (m-1)-1/2:
   // registers, or this thread's LDS slots
   R part[5] = {0, 0, 0, 0, 0};
@@ -410,12 +464,22 @@ stage_kernel(BatchArgs ba) {
   R inv_max = 0;
   bool bad = false;
 
-  // ---- prologue: primitives of planes z0-2 and z0-1
+  // ---- prologue: primitives of planes z0-2 and z0-1 (PPM: z0-3 .. z0)
   {
     Raw<R> r;
-    int k = wrapi(z0 - 2, a.nz);
-    load_raw<HY>(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
+    int k;
     Cell<R> w0;
+    if constexpr (PPM) {
+      k = wrapi(z0 - 3, a.nz);
+      load_raw<HY>(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
+      to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w0);
+      frame_vals<2>(w0, zm2);
+      k = wrapi(z0, a.nz);
+      load_raw<HY>(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
+      to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, wn);
+    }
+    k = wrapi(z0 - 2, a.nz);
+    load_raw<HY>(a, gi, gi1, gj, gj1, k, wrapi(k + 1, a.nz), r);
     to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w0);
     frame_vals<2>(w0, zm1);
     k = wrapi(z0 - 1, a.nz);
@@ -441,20 +505,17 @@ stage_kernel(BatchArgs ba) {
     Face<R> fx = {}, fy = {};
     if (do_x || corner_x) {
       const int fi = corner_x ? TX : ci, fj = corner_x ? -1 : cj;
-      R q[4][7];
+      R q[NS][7];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < NS; ++s) {
         Cell<R> c;
-        const int iw = T::w(fi - 2 + s, fj);
+        const int iw = T::w(fi - NS / 2 + s, fj);
         get_cell<HY>(S, iw, c);
         frame_vals<0>(c, q[s]);
       }
       R ql[7], qr[7];
 #pragma unroll
-      for (int v = 0; v < 7; ++v) {
-        ql[v] = recon_hi<RECON>(q[0][v], q[1][v], q[2][v]);
-        qr[v] = recon_lo<RECON>(q[1][v], q[2][v], q[3][v]);
-      }
+      for (int v = 0; v < 7; ++v) face_states<RECON>(q, v, ql[v], qr[v]);
       R bn = R(0);
       if constexpr (!HY) {
         if (corner_x) {
@@ -485,20 +546,17 @@ stage_kernel(BatchArgs ba) {
     }
     if (do_y || corner_y) {
       const int fi = corner_y ? -1 : ci, fj = corner_y ? TY : cj;
-      R q[4][7];
+      R q[NS][7];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < NS; ++s) {
         Cell<R> c;
-        const int iw = T::w(fi, fj - 2 + s);
+        const int iw = T::w(fi, fj - NS / 2 + s);
         get_cell<HY>(S, iw, c);
         frame_vals<1>(c, q[s]);
       }
       R ql[7], qr[7];
 #pragma unroll
-      for (int v = 0; v < 7; ++v) {
-        ql[v] = recon_hi<RECON>(q[0][v], q[1][v], q[2][v]);
-        qr[v] = recon_lo<RECON>(q[1][v], q[2][v], q[3][v]);
-      }
+      for (int v = 0; v < 7; ++v) face_states<RECON>(q, v, ql[v], qr[v]);
       R bn = R(0);
       if constexpr (!HY) {
         if (corner_y) {
@@ -532,11 +590,14 @@ stage_kernel(BatchArgs ba) {
 
     // ---------------- next plane's primitives and the z-face at m-1/2
     Cell<R> w1;
+    Cell<R> w2;  // PPM: plane m+2
     {
       Raw<R> r;
-      const int kn = wrapi(m + 1, a.nz);
+      const int kn = wrapi(PPM ? m + 2 : m + 1, a.nz);
       load_raw<HY>(a, gi, gi1, gj, gj1, kn, wrapi(kn + 1, a.nz), r);
-      to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, w1);
+      to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1,
+              PPM ? w2 : w1);
+      if constexpr (PPM) w1 = wn;
     }
     // own primitives of plane m, still in the LDS plane
     Cell<R> w0;
@@ -560,12 +621,25 @@ stage_kernel(BatchArgs ba) {
       frame_vals<2>(w0, qb);
       frame_vals<2>(w1, qc);
       R bot[7];
+      if constexpr (PPM) {
+        R qd[7];
+        frame_vals<2>(w2, qd);
 #pragma unroll
-      for (int v = 0; v < 7; ++v) {
-        R lo, hi;
-        recon_pair<RECON>(qa[v], qb[v], qc[v], lo, hi);
-        bot[v] = lo;
-        qa[v] = hi;  // becomes top of cell m
+        for (int v = 0; v < 7; ++v) {
+          R lo, hi;
+          ppm_faces(zm2[v], qa[v], qb[v], qc[v], qd[v], lo, hi);
+          bot[v] = lo;
+          zm2[v] = qa[v];  // plane m-1 becomes the window's far end
+          qa[v] = hi;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 7; ++v) {
+          R lo, hi;
+          recon_pair<RECON>(qa[v], qb[v], qc[v], lo, hi);
+          bot[v] = lo;
+          qa[v] = hi;  // becomes top of cell m
+        }
       }
       if (m >= z0) solve_face<2, SOLVER>(a, top7, bot, bz_m, fz);
 #pragma unroll
@@ -596,6 +670,7 @@ stage_kernel(BatchArgs ba) {
     {
       const int iw = T::w(ci, cj);
       put_cell<HY>(S, iw, w1);
+      if constexpr (PPM) wn = w2;
     }
     if (has_extra) {
       const int jw = T::w(xci, xcj);
@@ -745,7 +820,8 @@ stage_kernel(BatchArgs ba) {
 template <typename R, int SOLVER, int RECON, int EMF, int CT, int MODE, int TX, int TY>
 static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) {
   using T = Tile<TX, TY>;
-  const size_t lds = sizeof(SmemAll<R, TX, TY, SOLVER == SOLVER_HLLC>);
+  const size_t lds =
+      sizeof(SmemAll<R, TX, TY, SOLVER == SOLVER_HLLC, RECON == RECON_PPM ? 3 : 2>);
   auto fn = stage_kernel<R, SOLVER, RECON, EMF, CT, MODE, TX, TY>;
   if (prepare)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -778,20 +854,32 @@ static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) 
   return launch_mode<R, SOLVER, RECON, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
 }
 
+// PPM is built with the default EMF scheme and the face-field form of CT only.
+template <typename R, int SOLVER, int TX, int TY>
+static hipError_t launch_recon(const BatchArgs& ba, int recon, hipStream_t st, bool prepare) {
+  constexpr bool HY = SOLVER == SOLVER_HLLC;
+  if (recon == RECON_PPM) {
+    if (ba.ct != CT_FACE || (!HY && ba.emf != EMF_EC)) return hipErrorInvalidValue;
+    return launch_mode<R, SOLVER, RECON_PPM, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
+  }
+  const bool lim = recon == RECON_LIMO3;
+  if constexpr (HY) {
+    // HLLC (B = 0 problems): the EMFs vanish, so only the default scheme is built
+    if (ba.ct != CT_FACE) return hipErrorInvalidValue;
+    return lim ? launch_mode<R, SOLVER, RECON_LIMO3, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare)
+               : launch_mode<R, SOLVER, RECON_PLM, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
+  } else {
+    return lim ? launch_emf<R, SOLVER, RECON_LIMO3, TX, TY>(ba, st, prepare)
+               : launch_emf<R, SOLVER, RECON_PLM, TX, TY>(ba, st, prepare);
+  }
+}
+
 template <typename R, int TX, int TY>
 static hipError_t launch_tile(const BatchArgs& ba, int solver, int recon, hipStream_t st,
                               bool prepare) {
-  const bool lim = recon == RECON_LIMO3;
-  if (solver == SOLVER_HLLD)
-    return lim ? launch_emf<R, SOLVER_HLLD, RECON_LIMO3, TX, TY>(ba, st, prepare)
-               : launch_emf<R, SOLVER_HLLD, RECON_PLM, TX, TY>(ba, st, prepare);
-  if (solver == SOLVER_HLL)
-    return lim ? launch_emf<R, SOLVER_HLL, RECON_LIMO3, TX, TY>(ba, st, prepare)
-               : launch_emf<R, SOLVER_HLL, RECON_PLM, TX, TY>(ba, st, prepare);
-  // HLLC (B = 0 problems): the EMFs vanish, so only the default scheme is built
-  if (ba.ct != CT_FACE) return hipErrorInvalidValue;
-  return lim ? launch_mode<R, SOLVER_HLLC, RECON_LIMO3, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare)
-             : launch_mode<R, SOLVER_HLLC, RECON_PLM, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
+  if (solver == SOLVER_HLLD) return launch_recon<R, SOLVER_HLLD, TX, TY>(ba, recon, st, prepare);
+  if (solver == SOLVER_HLL) return launch_recon<R, SOLVER_HLL, TX, TY>(ba, recon, st, prepare);
+  return launch_recon<R, SOLVER_HLLC, TX, TY>(ba, recon, st, prepare);
 }
 
 // Raise the LDS limit of every mode of one (solver, reconstruction, EMF) choice.

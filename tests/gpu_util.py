@@ -33,7 +33,7 @@ def oracle_params(dims, l=(1.0, 1.0, 1.0), riemann="hlld", integrator="rk2", gam
                     riemann={"hlld": O.HLLD, "hll": O.HLL, "hllc": O.HLLC}[riemann],
                     integrator={"rk2": O.RK2, "euler": O.EULER, "rk3": O.RK3}[integrator],
                     emf={"ec": O.EMF_EC, "e0": O.EMF_E0, "arith": O.EMF_ARITH}[emf],
-                    recon={"plm": O.PLM, "limo3": O.LIMO3}[recon])
+                    recon={"plm": O.PLM, "limo3": O.LIMO3, "ppm": O.PPM}[recon])
 
 
 def run_both(state, dims, nsteps, l=(1.0, 1.0, 1.0), riemann="hlld", precision="fp64",

@@ -52,6 +52,14 @@ def test_workspace_bytes_and_argument_checks():
     q = make_params(8, 8, 8)
     q.emf = 7
     assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED
+    # PPM is built with face-field CT and (HLLD/HLL) the E^c scheme only
+    for kw in ({"recon": "ppm", "emf": "e0"}, {"recon": "ppm", "emf": "arith"},
+               {"recon": "ppm", "ct": "vecpot"}, {"recon": "ppm", "riemann": "hllc", "ct": "vecpot"}):
+        q = make_params(8, 8, 8, **kw)
+        assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED, kw
+    for kw in ({"recon": "ppm"}, {"recon": "ppm", "riemann": "hllc", "emf": "e0"}):
+        q = make_params(8, 8, 8, **kw)  # accepted up to the (missing) workspace
+        assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE, kw
     # no workspace / too small / misaligned
     q = make_params(8, 8, 8)
     assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE
