@@ -26,7 +26,7 @@ FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
 
 HLLD, HLL, HLLC = 0, 1, 2
 RK2, EULER, RK3 = 0, 1, 2
-EMF_EC, EMF_E0, EMF_ARITH = 0, 1, 2
+EMF_EC, EMF_E0, EMF_ARITH, EMF_UCT_HLL = 0, 1, 2, 3
 PLM, LIMO3, PPM = 0, 1, 2
 OK, ERR_INVALID_ARG, ERR_NOMEM, ERR_NONPHYSICAL = 0, -1, -2, -4
 

@@ -79,9 +79,14 @@ static int check_params(const orc_params* p) {
     return ORC_ERR_INVALID_ARG;
   if (p->integrator != ORC_RK2 && p->integrator != ORC_EULER && p->integrator != ORC_RK3)
     return ORC_ERR_INVALID_ARG;
-  if (p->emf != ORC_EMF_EC && p->emf != ORC_EMF_E0 && p->emf != ORC_EMF_ARITH)
+  if (p->emf != ORC_EMF_EC && p->emf != ORC_EMF_E0 && p->emf != ORC_EMF_ARITH &&
+      p->emf != ORC_EMF_UCT_HLL)
     return ORC_ERR_INVALID_ARG;
   if (p->recon != ORC_PLM && p->recon != ORC_LIMO3 && p->recon != ORC_PPM)
+    return ORC_ERR_INVALID_ARG;
+  /* the edge solve reconstructs face data with the three-cell limiters and needs
+   * a magnetic Riemann solver */
+  if (p->emf == ORC_EMF_UCT_HLL && (p->recon == ORC_PPM || p->riemann == ORC_HLLC))
     return ORC_ERR_INVALID_ARG;
   return ORC_OK;
 }
@@ -523,7 +528,7 @@ double orc_corner_emf_scheme(int scheme, double a1, double a2, double b1, double
 /* --------------------------------------------------------------- stage */
 
 enum { W_RHO, W_VX, W_VY, W_VZ, W_BX, W_BY, W_BZ, W_P, NW };
-enum { F_RHO, F_MX, F_MY, F_MZ, F_EN, F_B1, F_B2, F_CMAX, NF };
+enum { F_RHO, F_MX, F_MY, F_MZ, F_EN, F_B1, F_B2, F_CMAX, F_AP, F_AM, F_VT1, F_VT2, NF };
 
 typedef struct {
   double* w[NW];     /* primitives per cell */
@@ -622,6 +627,20 @@ static void faces(const grid_t* g, const orc_state* s, work_t* w, int d) {
         }
         long o = c[3];
         riemann(g->riemann, g->gamma, g->igm1, wl, wr, bnarr[o], fl, &cmax);
+        if (g->emf == ORC_EMF_UCT_HLL) {
+          /* what the edge solve takes from this face: the HLL speeds
+           * alpha+ = max(0, S_R), alpha- = max(0, -S_L) of the outer bounds, and
+           * the two transverse velocities averaged with the HLL weights, the
+           * velocity the HLL flux of B_t carries */
+          double sl, sr, cm;
+          outer_speeds(g->gamma, wl, wr, bnarr[o], &sl, &sr, &cm);
+          double ap = sr > 0.0 ? sr : 0.0;
+          double am = sl < 0.0 ? -sl : 0.0;
+          w->f[d][F_AP][o] = ap;
+          w->f[d][F_AM][o] = am;
+          w->f[d][F_VT1][o] = (ap * wl[2] + am * wr[2]) / (ap + am);
+          w->f[d][F_VT2][o] = (ap * wl[3] + am * wr[3]) / (ap + am);
+        }
         w->f[d][F_RHO][o] = fl[0];
         w->f[d][mom_of[d][0]][o] = fl[1];
         w->f[d][mom_of[d][1]][o] = fl[2];
@@ -685,6 +704,123 @@ static void emfs(const grid_t* g, work_t* w) {
   }
 }
 
+/* UCT-HLL corner EMFs (Sec. 2.4, the class that solves a 2D Riemann problem at
+ * each edge, Londrillo & Del Zanna 2004, in the form of Mignone & Del Zanna
+ * 2021).  For the edge along e with the cyclic plane (P, Q), E_e = v_Q B_P -
+ * v_P B_Q is split into two 1D HLL fluxes across the edge:
+ *   along Q, from the two P-faces that meet there: B_P (their normal field)
+ *   and their averaged v_Q, reconstructed along Q to the edge from either side;
+ *   along P, from the two Q-faces: B_Q and their averaged v_P, along P;
+ * each with the speeds alpha+- of the faces that the flux crosses (the larger
+ * of the two faces that share the edge):
+ *   F = (a+ vL bL + a- vR bR - a+ a- (bR - bL)) / (a+ + a-),
+ *   E_e = F_Q - F_P.
+ * On data that vary along one axis only this is the HLL face flux of the
+ * tangential field, as for the face-flux schemes. */
+static double uct_part(double ap, double am, double vl, double bl, double vr, double br) {
+  return ((ap * (vl * bl) + am * (vr * br)) - (ap * am) * (br - bl)) / (ap + am);
+}
+
+static double dmax(double a, double b) { return a > b ? a : b; }
+
+/* the value at the edge from the low side (upper face of the cell below) and
+ * from the high side, from four face values around it along the line */
+static void to_edge(int recon, const double* q, double* lo_side, double* hi_side) {
+  *lo_side = recon_hi(recon, q[0], q[1], q[2]);
+  *hi_side = recon_lo(recon, q[1], q[2], q[3]);
+}
+
+static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
+  double* const* fx = w->f[0];
+  double* const* fy = w->f[1];
+  double* const* fz = w->f[2];
+  const int r = g->recon;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < g->nz; ++k) {
+    int km = dn(k, g->nz);
+    for (int j = 0; j < g->ny; ++j) {
+      int jm = dn(j, g->ny);
+      for (int i = 0; i < g->nx; ++i) {
+        int im = dn(i, g->nx);
+        long c = at(g, i, j, k);
+        double b[4], v[4], bl, br, vl, vr;
+        /* E_z at (i-1/2, j-1/2, k): P = x, Q = y */
+        {
+          for (int q = 0; q < 4; ++q) {  /* y-faces (i-2 .. i+1, j-1/2) */
+            long f = at(g, wrap(i - 2 + q, g->nx), j, k);
+            b[q] = s->by[f];
+            v[q] = fy[F_VT2][f];  /* v_x on a y-face */
+          }
+          to_edge(r, b, &bl, &br);
+          to_edge(r, v, &vl, &vr);
+          long cjm = at(g, i, jm, k);
+          double fp = uct_part(dmax(fx[F_AP][cjm], fx[F_AP][c]), dmax(fx[F_AM][cjm], fx[F_AM][c]),
+                               vl, bl, vr, br);
+          for (int q = 0; q < 4; ++q) {  /* x-faces (i-1/2, j-2 .. j+1) */
+            long f = at(g, i, wrap(j - 2 + q, g->ny), k);
+            b[q] = s->bx[f];
+            v[q] = fx[F_VT1][f];  /* v_y on an x-face */
+          }
+          to_edge(r, b, &bl, &br);
+          to_edge(r, v, &vl, &vr);
+          long cim = at(g, im, j, k);
+          double fq = uct_part(dmax(fy[F_AP][cim], fy[F_AP][c]), dmax(fy[F_AM][cim], fy[F_AM][c]),
+                               vl, bl, vr, br);
+          w->ed[2][c] = fq - fp;
+        }
+        /* E_x at (i, j-1/2, k-1/2): P = y, Q = z */
+        {
+          for (int q = 0; q < 4; ++q) {  /* z-faces (i, j-2 .. j+1, k-1/2) */
+            long f = at(g, i, wrap(j - 2 + q, g->ny), k);
+            b[q] = s->bz[f];
+            v[q] = fz[F_VT2][f];  /* v_y on a z-face */
+          }
+          to_edge(r, b, &bl, &br);
+          to_edge(r, v, &vl, &vr);
+          long ckm = at(g, i, j, km);
+          double fp = uct_part(dmax(fy[F_AP][ckm], fy[F_AP][c]), dmax(fy[F_AM][ckm], fy[F_AM][c]),
+                               vl, bl, vr, br);
+          for (int q = 0; q < 4; ++q) {  /* y-faces (i, j-1/2, k-2 .. k+1) */
+            long f = at(g, i, j, wrap(k - 2 + q, g->nz));
+            b[q] = s->by[f];
+            v[q] = fy[F_VT1][f];  /* v_z on a y-face */
+          }
+          to_edge(r, b, &bl, &br);
+          to_edge(r, v, &vl, &vr);
+          long cjm = at(g, i, jm, k);
+          double fq = uct_part(dmax(fz[F_AP][cjm], fz[F_AP][c]), dmax(fz[F_AM][cjm], fz[F_AM][c]),
+                               vl, bl, vr, br);
+          w->ed[0][c] = fq - fp;
+        }
+        /* E_y at (i-1/2, j, k-1/2): P = z, Q = x */
+        {
+          for (int q = 0; q < 4; ++q) {  /* x-faces (i-1/2, j, k-2 .. k+1) */
+            long f = at(g, i, j, wrap(k - 2 + q, g->nz));
+            b[q] = s->bx[f];
+            v[q] = fx[F_VT2][f];  /* v_z on an x-face */
+          }
+          to_edge(r, b, &bl, &br);
+          to_edge(r, v, &vl, &vr);
+          long cim = at(g, im, j, k);
+          double fp = uct_part(dmax(fz[F_AP][cim], fz[F_AP][c]), dmax(fz[F_AM][cim], fz[F_AM][c]),
+                               vl, bl, vr, br);
+          for (int q = 0; q < 4; ++q) {  /* z-faces (i-2 .. i+1, j, k-1/2) */
+            long f = at(g, wrap(i - 2 + q, g->nx), j, k);
+            b[q] = s->bz[f];
+            v[q] = fz[F_VT1][f];  /* v_x on a z-face */
+          }
+          to_edge(r, b, &bl, &br);
+          to_edge(r, v, &vl, &vr);
+          long ckm = at(g, i, j, km);
+          double fq = uct_part(dmax(fx[F_AP][ckm], fx[F_AP][c]), dmax(fx[F_AM][ckm], fx[F_AM][c]),
+                               vl, bl, vr, br);
+          w->ed[1][c] = fq - fp;
+        }
+      }
+    }
+  }
+}
+
 /* One application of the stage operator S_dt (steps S1-S8) to src, written to
  * dst; if base is given, dst = ws S_dt(src) + w0 base (later stages of a
  * Runge-Kutta cycle, Sec. 2.7; base and dst may be the same arrays).  If maxinv
@@ -698,7 +834,10 @@ static int stage(const grid_t* g, const orc_state* src, const orc_state* base, d
                  const orc_vpot* asrc, const orc_vpot* abase, orc_vpot* adst) {
   int bad = prim_all(g, src, w);
   for (int d = 0; d < 3; ++d) faces(g, src, w, d);
-  emfs(g, w);
+  if (g->emf == ORC_EMF_UCT_HLL)
+    emfs_uct(g, src, w);
+  else
+    emfs(g, w);
   double tx = dt * g->idl[0], ty = dt * g->idl[1], tz = dt * g->idl[2];
   double mx = 0.0;
   double* const* fx = w->f[0];

@@ -21,8 +21,10 @@ extern "C" {
 
 enum { ORC_HLLD = 0, ORC_HLL = 1, ORC_HLLC = 2 }; /* HLLC: hydrodynamics, B = 0 */
 enum { ORC_RK2 = 0, ORC_EULER = 1, ORC_RK3 = 2 };
-/* corner-EMF schemes of Sec. 2.4: E^c (default), E^0, arithmetic average */
-enum { ORC_EMF_EC = 0, ORC_EMF_E0 = 1, ORC_EMF_ARITH = 2 };
+/* corner-EMF schemes of Sec. 2.4: E^c (default), E^0, arithmetic average (all
+ * from the face fluxes), and UCT-HLL, a 2D HLL Riemann solve at each edge
+ * (MHD solvers with PLM or LimO3 only) */
+enum { ORC_EMF_EC = 0, ORC_EMF_E0 = 1, ORC_EMF_ARITH = 2, ORC_EMF_UCT_HLL = 3 };
 /* reconstructions of Sec. 2.3: van Leer PLM (default), LimO3, PPM */
 enum { ORC_PLM = 0, ORC_LIMO3 = 1, ORC_PPM = 2 };
 
@@ -40,7 +42,7 @@ typedef struct {
   double cfl;          /* sigma_CFL of eq. (cfl), in (0, 1) */
   int riemann;         /* ORC_HLLD, ORC_HLL or ORC_HLLC */
   int integrator;      /* ORC_RK2, ORC_EULER or ORC_RK3 (Tab. weights) */
-  int emf;             /* ORC_EMF_EC, ORC_EMF_E0 or ORC_EMF_ARITH */
+  int emf;             /* ORC_EMF_EC, ORC_EMF_E0, ORC_EMF_ARITH or ORC_EMF_UCT_HLL */
   int recon;           /* ORC_PLM, ORC_LIMO3 or ORC_PPM */
 } orc_params;
 
