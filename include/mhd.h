@@ -9,8 +9,8 @@
  *   2.4); per stage: primitive reconstruction with the van Leer limiter, LimO3 or
  *   PPM (Sec. 2.3),
  *   an HLLD or HLL Riemann solve on every x, y and z face (Sec. 2.3), corner EMFs
- *   by the upwind-by-contact E^c scheme or its E^0 and arithmetic variants
- *   (Sec. 2.4), the flux-divergence update of U
+ *   by the upwind-by-contact E^c scheme, its E^0 and arithmetic variants, or
+ *   the UCT-HLL edge solve (Sec. 2.4), the flux-divergence update of U
  *   and the constrained-transport update of face B (eq. ind_short); stages combined
  *   as U_s = w_s U* + w0_s U_0 (Sec. 2.7, Tab. weights); time step from eq. (cfl).
  * Energy is E = p/(gamma-1) + rho v^2/2 + B^2/2, dimensionless units without 4 pi.
@@ -56,9 +56,16 @@ typedef enum { MHD_FP64 = 0, MHD_FP32 = 1 } mhd_precision;
  * problems: with it the field is neither read nor evolved (the face field is
  * written as zero), and the stage kernel skips the EMF work entirely. */
 typedef enum { MHD_HLLD = 0, MHD_HLL = 1, MHD_HLLC = 2 } mhd_riemann;
-/* Corner-EMF schemes of Sec. 2.4 (Gardiner & Stone 2005): E^c (default), E^0
- * and the arithmetic mean of the four face EMFs. */
-typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2 } mhd_emf;
+/* Corner-EMF schemes of Sec. 2.4: from the face fluxes (Gardiner & Stone
+ * 2005) E^c (default), E^0 and the arithmetic mean of the four face EMFs; and
+ * UCT-HLL, a 2D HLL Riemann solve at each edge (Londrillo & Del Zanna 2004, in
+ * the form of Mignone & Del Zanna 2021), which splits each edge EMF into two 1D
+ * HLL fluxes across the edge from the faces' normal fields and HLL-averaged
+ * transverse velocities reconstructed to it.  UCT-HLL is built for HLLD/HLL
+ * with MHD_PLM and MHD_CT_FACE (else MHD_ERR_UNSUPPORTED); it runs two extra
+ * one-thread-per-cell launches per stage and needs 15 more arrays of one field
+ * in the workspace (mhd_workspace_bytes accounts for them). */
+typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2, MHD_EMF_UCT_HLL = 3 } mhd_emf;
 /* Reconstructions of Sec. 2.3, all on the primitives: van Leer PLM (default),
  * the compact third-order LimO3 limiter (Cada & Torrilhon 2009), and PPM
  * (Colella & Woodward 1984) with the extremum-preserving limiter of Colella &

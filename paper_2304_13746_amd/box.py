@@ -19,7 +19,7 @@ FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
 PRECISION = {"fp64": L.MHD_FP64, "fp32": L.MHD_FP32}
 RIEMANN = {"hlld": L.MHD_HLLD, "hll": L.MHD_HLL, "hllc": L.MHD_HLLC}
 INTEGRATOR = {"rk2": L.MHD_RK2, "euler": L.MHD_EULER, "rk3": L.MHD_RK3}
-EMF = {"ec": L.MHD_EMF_EC, "e0": L.MHD_EMF_E0, "arith": L.MHD_EMF_ARITH}
+EMF = {"ec": L.MHD_EMF_EC, "e0": L.MHD_EMF_E0, "arith": L.MHD_EMF_ARITH, "uct_hll": L.MHD_EMF_UCT_HLL}
 RECON = {"plm": L.MHD_PLM, "limo3": L.MHD_LIMO3, "ppm": L.MHD_PPM}
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
 
@@ -51,8 +51,10 @@ def make_params(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, gamma=5.0 / 3.0, cfl=0.3, pr
     return p
 
 
-def workspace_bytes(nx, ny, nz, precision="fp64", tile=0, integrator="rk2", ct="face") -> int:
-    p = make_params(nx, ny, nz, precision=precision, tile=tile, integrator=integrator, ct=ct)
+def workspace_bytes(nx, ny, nz, precision="fp64", tile=0, integrator="rk2", ct="face",
+                    emf="ec") -> int:
+    p = make_params(nx, ny, nz, precision=precision, tile=tile, integrator=integrator, ct=ct,
+                    emf=emf)
     return int(L.lib().mhd_workspace_bytes(C.byref(p)))
 
 

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmhd.so")
 # a plain host program that drives the library through the C ABI only
 EXAMPLE = os.path.join(HERE, "mhd_abi_example")
-SOURCES = ["mhd_api.hip", "mhd_stage_f64.hip", "mhd_stage_f32.hip", "mhd_vpot.hip"]
+SOURCES = ["mhd_api.hip", "mhd_stage_f64.hip", "mhd_stage_f32.hip", "mhd_vpot.hip", "mhd_uct.hip"]
 ARCH = os.environ.get("MHD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",

@@ -22,6 +22,7 @@ struct mhd_ctx {
   int nbuf;
   int nfield;  // fields per buffer: 8, or 11 with the vector-potential form
   int cur;           // buffer holding the state
+  void* uct;         // UCT-HLL scratch (kUctArrays arrays of one field), or null
   Scalars* sc;       // device scalars
   BoxDesc* desc;     // device copy of this box's descriptor
   double* diag_part; // per-block diagnostic partials
@@ -54,6 +55,8 @@ size_t field_bytes(const mhd_params* p) {
 // state buffers a context needs: U_0 and one per intermediate stage result
 int nbuf_of(const mhd_params* p) { return p->integrator == MHD_RK3 ? 3 : 2; }
 int nfield_of(const mhd_params* p) { return p->ct == MHD_CT_VECPOT ? 11 : 8; }
+// scratch arrays of one field each: the UCT-HLL face data and edge EMFs
+int nscratch_of(const mhd_params* p) { return p->emf == MHD_EMF_UCT_HLL ? kUctArrays : 0; }
 
 // ---- cycle control kernels (one thread): everything stays on the device
 
@@ -255,6 +258,34 @@ hipError_t launch_stage(mhd_ctx* const* c, const Roles* r, int n, int mode, doub
   return hipSuccess;
 }
 
+// UCT-HLL after a stage launch (mode 0: first stage, 1: combining stage): the
+// edge EMFs from the exported face data, then the face-field update.
+hipError_t launch_uct(mhd_ctx* const* c, const Roles* r, int n, int mode, double w, double w0,
+                      hipStream_t st) {
+  for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+    const int m = n - i0 < kMaxBatch ? n - i0 : kMaxBatch;
+    BatchArgs ba = {};
+    ba.nbox = m;
+    ba.mode = mode;
+    ba.w = w;
+    ba.w0 = w0;
+    int g = 0;
+    for (int i = 0; i < m; ++i) {
+      ba.desc[i] = c[i0 + i]->desc;
+      ba.start[i] = g;
+      ba.src[i] = r[i0 + i].src;
+      ba.dst[i] = r[i0 + i].dst;
+      ba.base[i] = r[i0 + i].base;
+      g += (int)((c[i0 + i]->ncell + kUctBlock - 1) / kUctBlock);
+    }
+    ba.start[m] = g;
+    ba.total = g;
+    hipError_t e = c[i0]->p.precision == MHD_FP32 ? uct_f32(ba, st) : uct_f64(ba, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Vector-potential form after a stage launch (mode 0: first stage, 1: combining
 // stage): A update on every edge, then the face field from curl A; update =
 // false runs only the curl (deriving B from a potential the caller set).
@@ -320,6 +351,7 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
   if (launch_ctl(true, act, m, ts, st) != hipSuccess) return MHD_ERR_HIP;
   const int integ = c[0]->p.integrator;
   const bool vp = c[0]->p.ct == MHD_CT_VECPOT;
+  const bool uct = c[0]->p.emf == MHD_EMF_UCT_HLL;
   for (int cyc = 0; cyc < maxs; ++cyc) {
     m = 0;
     for (int i = 0; i < n; ++i)
@@ -330,9 +362,11 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
       roles[i] = {(unsigned char)u0, (unsigned char)(u0 == 0 ? 1 : 0), (unsigned char)u0};
     }
     // with the vector-potential form every stage is followed by the A update
-    // and the curl (same roles and weights)
+    // and the curl, with UCT-HLL by the edge solve and the face-field update
+    // (same roles and weights)
     auto stage = [&](int mode, double w, double w0) -> bool {
       if (launch_stage(act, roles, m, mode, w, w0, st) != hipSuccess) return false;
+      if (uct && launch_uct(act, roles, m, mode, w, w0, st) != hipSuccess) return false;
       return !vp || launch_vpot(act, roles, m, mode, w, w0, true, st) == hipSuccess;
     };
     if (!stage(0, 1.0, 0.0)) return MHD_ERR_HIP;
@@ -399,6 +433,8 @@ int apply_shape(mhd_ctx* c, int tile, int zchunk) {
   for (int k = 0; k < 3; ++k) d.idl[k] = c->idl[k];
   d.gamma = p->gamma;
   d.sc = c->sc;
+  d.uct = c->uct;
+  d.ustride = (long long)(field_bytes(p) / c->elem);
   if (hipStreamSynchronize(c->stream) != hipSuccess ||
       hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess)
     return MHD_ERR_HIP;
@@ -415,7 +451,8 @@ bool same_group(mhd_ctx* const* ctxs, int n) {
     const mhd_ctx* c = ctxs[i];
     if (c->p.precision != c0->p.precision || c->p.riemann != c0->p.riemann ||
         c->p.integrator != c0->p.integrator || c->p.emf != c0->p.emf ||
-        c->p.recon != c0->p.recon || c->tile != c0->tile || c->device != c0->device)
+        c->p.recon != c0->p.recon || c->p.ct != c0->p.ct || c->tile != c0->tile ||
+        c->device != c0->device)
       return false;
   }
   return true;
@@ -444,7 +481,7 @@ size_t mhd_workspace_bytes(const mhd_params* p) {
   if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return 0;
   return align_up(sizeof(Scalars)) + align_up(sizeof(BoxDesc)) +
          align_up(sizeof(double) * kDiagBlocks * kDiagVals) +
-         (size_t)nfield_of(p) * nbuf_of(p) * field_bytes(p);
+         ((size_t)nfield_of(p) * nbuf_of(p) + nscratch_of(p)) * field_bytes(p);
 }
 
 int mhd_create(const mhd_params* p, mhd_ctx** out) {
@@ -457,7 +494,12 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   if (p->precision != MHD_FP64 && p->precision != MHD_FP32) return MHD_ERR_INVALID_ARG;
   if (p->riemann != MHD_HLLD && p->riemann != MHD_HLL && p->riemann != MHD_HLLC)
     return MHD_ERR_INVALID_ARG;
-  if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH)
+  if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH &&
+      p->emf != MHD_EMF_UCT_HLL)
+    return MHD_ERR_UNSUPPORTED;
+  // UCT-HLL is built for the MHD solvers with PLM and face-field CT
+  if (p->emf == MHD_EMF_UCT_HLL &&
+      (p->riemann == MHD_HLLC || p->recon != MHD_PLM || p->ct != MHD_CT_FACE))
     return MHD_ERR_UNSUPPORTED;
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3 && p->recon != MHD_PPM)
     return MHD_ERR_UNSUPPORTED;
@@ -510,6 +552,8 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
       c->buf[b][f] = w;
       w += fb;
     }
+  c->uct = nscratch_of(p) > 0 ? (void*)w : nullptr;
+  w += (size_t)nscratch_of(p) * fb;
   c->cur = 0;
   c->diag_blocks = kDiagBlocks;
   if (apply_shape(c, tile, p->zchunk) != MHD_OK) {

@@ -444,7 +444,7 @@ __device__ __forceinline__ void riemann(R gamma, R igm1, const Prim<R>& l, const
 // derivative terms by the sign of the face mass flux, E^0 averages the two
 // candidates on every side, the arithmetic scheme is the mean of the four face
 // EMFs alone.
-enum { EMF_EC = 0, EMF_E0 = 1, EMF_ARITH = 2 };
+enum { EMF_EC = 0, EMF_E0 = 1, EMF_ARITH = 2, EMF_UCT = 3 };  // UCT: see mhd_uct.hip
 
 // Upwind choice by the sign of a mass flux; zero averages the two candidates.
 template <typename R>

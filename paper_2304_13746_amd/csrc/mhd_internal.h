@@ -67,6 +67,11 @@ struct BoxDesc {
   double gamma;
   double b0[3];           // mean field of the vector-potential form
   Scalars* sc;
+  // UCT-HLL scratch: 15 arrays of one cell each, ustride elements apart: per
+  // face direction d the HLL speeds alpha+, alpha- and the averaged transverse
+  // velocities vt1, vt2 (array 4 d + q), then the edge EMFs E_x, E_y, E_z
+  void* uct;
+  long long ustride;
 };
 
 // One stage launch over up to kMaxBatch boxes: global block g belongs to the
@@ -94,6 +99,13 @@ hipError_t stage_f64(const BatchArgs& b, int tile, int solver, int recon, hipStr
 constexpr int kVpotBlock = 256;
 hipError_t vpot_update_f64(const BatchArgs& b, hipStream_t st);
 hipError_t vpot_curl_f64(const BatchArgs& b, hipStream_t st);
+// UCT-HLL after a stage launch: the edge EMFs from the face data the stage
+// kernel exported, then the face-field update B_dst = w (B_src - dt curl E) +
+// w0 B_base.  ba.start[] counts blocks of kUctBlock cells.
+constexpr int kUctBlock = 256;
+constexpr int kUctArrays = 15;
+hipError_t uct_f64(const BatchArgs& b, hipStream_t st);
+hipError_t uct_f32(const BatchArgs& b, hipStream_t st);
 hipError_t stage_f32(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
                      bool prepare);
 int tile_dims(int tile, int* tx, int* ty);

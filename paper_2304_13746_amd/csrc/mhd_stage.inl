@@ -43,6 +43,8 @@ struct StageArgs {
   R gamma, gm1, igm1;
   const Scalars* sc;  // device scalars: dt of this cycle, CFL maximum, status
   Scalars* scw;
+  R* uf;              // UCT-HLL face data (see BoxDesc::uct)
+  long long ustride;
 };
 
 enum { MODE_STAGE1 = 0, MODE_COMBINE = 1, MODE_MEASURE = 2 };
@@ -185,16 +187,40 @@ struct Face {
   R cons[5];  // grid-frame flux of rho, mx, my, mz, E
   R fb1, fb2; // face-frame fluxes of B_t1, B_t2
   R cmax;
+  R ap, am, vt1, vt2;  // UCT-HLL: HLL speeds and averaged transverse velocities
 };
 
-template <int D, int SOLVER, typename R>
+template <int D, int SOLVER, bool UCT = false, typename R>
 __device__ __forceinline__ void solve_face(const StageArgs<R>& a, const R* ql, const R* qr, R bn,
                                            Face<R>& out) {
   R f[7];
-  riemann<SOLVER>(a.gamma, a.igm1, as_prim(ql), as_prim(qr), bn, f, out.cmax);
+  const Prim<R> l = as_prim(ql), r = as_prim(qr);
+  riemann<SOLVER>(a.gamma, a.igm1, l, r, bn, f, out.cmax);
   to_grid<D>(f, out.cons);
   out.fb1 = f[5];
   out.fb2 = f[6];
+  if constexpr (UCT) {
+    // alpha+ = max(0, S_R), alpha- = max(0, -S_L) of the outer bounds and the
+    // transverse velocities averaged with the HLL weights
+    R sl, sr, cm;
+    outer_speeds(a.gamma, l, r, bn, sl, sr, cm);
+    const R ap = sr > R(0) ? sr : R(0);
+    const R am = sl < R(0) ? -sl : R(0);
+    out.ap = ap;
+    out.am = am;
+    out.vt1 = dvd(ap * l.v1 + am * r.v1, ap + am);
+    out.vt2 = dvd(ap * l.v2 + am * r.v2, ap + am);
+  }
+}
+
+// UCT-HLL face data of a face solved by its owner, stored at the face's cell
+template <int D, typename R>
+__device__ __forceinline__ void put_uct(const StageArgs<R>& a, long long o, const Face<R>& f) {
+  R* u = a.uf + (long long)(4 * D) * a.ustride + o;
+  gst(u, 0, f.ap);
+  gst(u, a.ustride, f.am);
+  gst(u, 2 * a.ustride, f.vt1);
+  gst(u, 3 * a.ustride, f.vt2);
 }
 
 // Tile geometry: TX x TY interior, threads own interior columns then the ring.
@@ -357,6 +383,11 @@ stage_kernel(BatchArgs ba) {
   // field is written as zero, and the ring columns solve only the x- and
   // y-faces the tile's own cells need
   constexpr bool HY = SOLVER == SOLVER_HLLC;
+  // UCT-HLL forms its edge EMFs in launches of its own: this kernel exports the
+  // face data they need and, like the hydrodynamic path, does no corner-EMF work
+  // and solves only the faces the tile's own cells need (it leaves B alone)
+  constexpr bool UCT = EMF == EMF_UCT;
+  constexpr bool NE = HY || UCT;
   using SA_t = SmemAll<R, TX, TY, HY, H>;
   SA_t& SA = *reinterpret_cast<SA_t*>(smem_raw);
   auto& S = SA.s;
@@ -396,6 +427,8 @@ stage_kernel(BatchArgs ba) {
     a.igm1 = (R)(1.0 / (d->gamma - 1.0));
     a.sc = d->sc;
     a.scw = d->sc;
+    a.uf = static_cast<R*>(d->uct);
+    a.ustride = d->ustride;
   }
   const int tx = b % a.ntx;
   const int ty = (b / a.ntx) % a.nty;
@@ -414,15 +447,15 @@ stage_kernel(BatchArgs ba) {
   const bool interior = ci >= 0 && ci < TX && cj >= 0 && cj < TY;
   const bool real = interior && (x0 + ci < a.nx) && (y0 + cj < a.ny);
   const bool left = ci == -1, right = ci == TX, bottom = cj == -1, top = cj == TY;
-  const bool do_x = HY ? (interior || right) : !left;   // own x-face (ci-1/2, cj)
-  const bool do_y = HY ? (interior || top) : !bottom;   // own y-face (ci, cj-1/2)
+  const bool do_x = NE ? (interior || right) : !left;   // own x-face (ci-1/2, cj)
+  const bool do_y = NE ? (interior || top) : !bottom;   // own y-face (ci, cj-1/2)
   const bool do_ez = !left && !bottom;       // E_z at (ci-1/2, cj-1/2)
   const bool do_ex = interior || top;        // E_x at (ci, cj-1/2)
   const bool do_ey = interior || right;      // E_y at (ci-1/2, cj)
   // corner faces: the first left-ring thread solves x-face (TX, -1), the first
   // bottom-ring thread y-face (-1, TY)
-  const bool corner_x = !HY && (t == TX * TY);
-  const bool corner_y = !HY && (t == TX * TY + 2 * TY);
+  const bool corner_x = !NE && (t == TX * TY);
+  const bool corner_y = !NE && (t == TX * TY + 2 * TY);
   const int ex_me = T::e(ci, cj);
 
   // halo primitive item of this thread (if any)
@@ -526,12 +559,15 @@ stage_kernel(BatchArgs ba) {
           bn = gld(a.src[5], (long long)km * plane + col);
         }
       }
-      solve_face<0, SOLVER>(a, ql, qr, bn, fx);
+      solve_face<0, SOLVER, UCT>(a, ql, qr, bn, fx);
       // the previous plane's exports were consumed before the last barrier
-      if constexpr (HY) {
+      if constexpr (NE) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) S.xcons[q][ex_me] = fx.cons[q];
         S.xcmax[ex_me] = fx.cmax;
+        if constexpr (UCT) {
+          if (real && m >= z0 && m < z1) put_uct<0>(a, (long long)km * plane + col, fx);
+        }
       } else if (corner_x) {
         const int ec = T::e(TX, -1);
         S.xez[ec] = -fx.fb1;
@@ -567,11 +603,14 @@ stage_kernel(BatchArgs ba) {
           bn = gld(a.src[6], (long long)km * plane + col);
         }
       }
-      solve_face<1, SOLVER>(a, ql, qr, bn, fy);
-      if constexpr (HY) {
+      solve_face<1, SOLVER, UCT>(a, ql, qr, bn, fy);
+      if constexpr (NE) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) S.ycons[q][ex_me] = fy.cons[q];
         S.ycmax[ex_me] = fy.cmax;
+        if constexpr (UCT) {
+          if (real && m >= z0 && m < z1) put_uct<1>(a, (long long)km * plane + col, fy);
+        }
       } else if (corner_y) {
         const int ec = T::e(-1, TY);
         S.yez[ec] = fy.fb2;
@@ -614,7 +653,7 @@ stage_kernel(BatchArgs ba) {
       to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, wx);
     }
     Face<R> fz = {};
-    if (!HY || interior) {  // hydrodynamics needs the z-faces of its own cells only
+    if (!NE || interior) {  // without corner EMFs only the tile's own z-faces are needed
       R qa[7], qb[7], qc[7];
 #pragma unroll
       for (int v = 0; v < 7; ++v) qa[v] = zm1[v];
@@ -641,7 +680,10 @@ stage_kernel(BatchArgs ba) {
           qa[v] = hi;  // becomes top of cell m
         }
       }
-      if (m >= z0) solve_face<2, SOLVER>(a, top7, bot, bz_m, fz);
+      if (m >= z0) solve_face<2, SOLVER, UCT>(a, top7, bot, bz_m, fz);
+      if constexpr (UCT) {
+        if (real && m >= z0 && m < z1) put_uct<2>(a, (long long)km * plane + col, fz);
+      }
 #pragma unroll
       for (int v = 0; v < 7; ++v) {
         top7[v] = qa[v];
@@ -654,7 +696,7 @@ stage_kernel(BatchArgs ba) {
     const R erz = w0.vy * w0.bx - w0.vx * w0.by;
     if (real && m >= z0 && m < z1) bad |= bad_cell(w0);
 
-    if constexpr (!HY) {
+    if constexpr (!NE) {
       S.zex[ex_me] = fz.fb2;
       S.zey[ex_me] = -fz.fb1;
       S.zmass[ex_me] = fz.cons[0];
@@ -680,7 +722,7 @@ stage_kernel(BatchArgs ba) {
 
     // ---------------- C: corner EMFs, cell update of plane m-1
     R ez_new = 0, ex_new = 0, ey_new = 0;
-    if constexpr (!HY) {
+    if constexpr (!NE) {
     if (do_ez && m >= z0 && m < z1) {
       const int e_s = T::e(ci, cj - 1), e_w = T::e(ci - 1, cj), e_sw = T::e(ci - 1, cj - 1);
       ez_new = corner_emf<EMF>(S.xez[ex_me], S.xez[e_s], S.yez[ex_me], S.yez[e_w], S.erz[e_sw],
@@ -699,7 +741,7 @@ stage_kernel(BatchArgs ba) {
                             ery, fz.cons[0], S.zmass[e_w], xmass_now, xmass_prev);
       }
     }
-    }  // !HY
+    }  // !NE
     // partial update of cell m (x then y), kept for the next iteration
     R part_new[5];
     R cxy_new = 0;
@@ -736,6 +778,8 @@ stage_kernel(BatchArgs ba) {
         if constexpr (HY) {
           gst(a.dst[5], o, R(0));
           gst(a.dst[6], o, R(0));
+        } else if constexpr (UCT) {
+          // the face field is updated after the edge solve
         } else if constexpr (CT == CT_FACE) {
           const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
           R bxn = (gld(a.src[5], o) - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
@@ -752,7 +796,7 @@ stage_kernel(BatchArgs ba) {
     __syncthreads();  // reads of corner-EMF buffers of plane m-1 done
 
     // ---------------- D: publish corner EMFs; E: B_z on face m-1/2
-    if constexpr (!HY) {
+    if constexpr (!NE) {
       if (do_ez) S.ez[ex_me] = ez_new;
       if (do_ex) S.ex[ex_me] = ex_new;
       if (do_ey) S.ey[ex_me] = ey_new;
@@ -763,6 +807,8 @@ stage_kernel(BatchArgs ba) {
         const long long o = (long long)km * plane + col;
         if constexpr (HY) {
           gst(a.dst[7], o, R(0));
+        } else if constexpr (UCT) {
+          // the face field is updated after the edge solve
         } else if constexpr (CT == CT_FACE) {
           const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
           R bzn = (bz_m - tau_x * (S.ey[e_e] - ey_new)) + tau_y * (S.ex[e_n] - ex_new);
@@ -845,6 +891,13 @@ static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) 
   if (ba.ct == CT_VECPOT) {
     if constexpr (sizeof(R) == 8) {
       if (ba.emf == EMF_EC) return launch_mode<R, SOLVER, RECON, EMF_EC, CT_VECPOT, TX, TY>(ba, st, prepare);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (ba.emf == EMF_UCT) {
+    // UCT-HLL is built with PLM and the face-field form
+    if constexpr (RECON == RECON_PLM) {
+      if (ba.ct == CT_FACE) return launch_mode<R, SOLVER, RECON, EMF_UCT, CT_FACE, TX, TY>(ba, st, prepare);
     }
     return hipErrorInvalidValue;
   }

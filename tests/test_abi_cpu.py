@@ -57,9 +57,18 @@ def test_workspace_bytes_and_argument_checks():
                {"recon": "ppm", "ct": "vecpot"}, {"recon": "ppm", "riemann": "hllc", "ct": "vecpot"}):
         q = make_params(8, 8, 8, **kw)
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED, kw
-    for kw in ({"recon": "ppm"}, {"recon": "ppm", "riemann": "hllc", "emf": "e0"}):
+    # UCT-HLL: MHD solvers, PLM, face-field CT
+    for kw in ({"emf": "uct_hll", "riemann": "hllc"}, {"emf": "uct_hll", "recon": "limo3"},
+               {"emf": "uct_hll", "recon": "ppm"}, {"emf": "uct_hll", "ct": "vecpot"}):
+        q = make_params(8, 8, 8, **kw)
+        assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED, kw
+    for kw in ({"recon": "ppm"}, {"recon": "ppm", "riemann": "hllc", "emf": "e0"},
+               {"emf": "uct_hll"}, {"emf": "uct_hll", "riemann": "hll", "precision": "fp32"}):
         q = make_params(8, 8, 8, **kw)  # accepted up to the (missing) workspace
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE, kw
+    # UCT-HLL takes 15 more arrays of one field in the workspace
+    pu = make_params(32, 32, 32, precision="fp64", emf="uct_hll")
+    assert L.mhd_workspace_bytes(C.byref(pu)) - n64 == 15 * 32 ** 3 * 8
     # no workspace / too small / misaligned
     q = make_params(8, 8, 8)
     assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE
