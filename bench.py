@@ -118,25 +118,28 @@ def roofline(precision: str, launch_ms: float):
                     "algorithmic_bytes_per_launch": bytes_per_launch}}
 
 
+CPU_CYCLES = 10  # about 10-15 s of oracle work on 16 host cores
+
+
 def cpu_baseline(state):
-    """The FP64 oracle on the host cores: 2 RK2 cycles of the same 256^3 input
-    (after its first-dt pre-pass), reported as cell-updates/s."""
+    """The FP64 oracle on the host cores: CPU_CYCLES RK2 cycles of the same 256^3
+    input (after its first-dt pre-pass), reported as cell-updates/s."""
     import oracle as O
 
     s = O.copy_state(state)
     p = O.Params(N, N, N)
     mi = O.max_invdt(p, s)
     t0 = time.perf_counter()
-    O.step(p, s, 0.0, 0.3 / mi, 2)
+    O.step(p, s, 0.0, 0.3 / mi, CPU_CYCLES)
     el = time.perf_counter() - t0
-    return {"value": round(2 * N ** 3 / el, 1), "unit": "cell-updates/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"2 RK2 cycles of the same 256^3 FP64 input ({el:.1f} s, OpenMP)",
+    return {"value": round(CPU_CYCLES * N ** 3 / el, 1), "unit": "cell-updates/s",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{CPU_CYCLES} RK2 cycles of the same 256^3 FP64 input ({el:.1f} s, OpenMP)",
             "error_vs_oracle": errors_vs_oracle(state, s)}
 
 
 def errors_vs_oracle(state, ref):
-    """Errors of the GPU results after the same 2 cycles against the oracle's:
+    """Errors of the GPU results after the same cycles against the oracle's:
     FP64 (expected bit-identical) and FP32 (input rounded to FP32 by the
     library), per quantity as max|gpu - oracle| / max|oracle| and as the ratio
     of L2 norms."""
@@ -148,7 +151,7 @@ def errors_vs_oracle(state, ref):
     for prec in ("fp64", "fp32"):
         box = MHDBox(N, N, N, precision=prec)
         box.set_state(state)
-        box.step(2)
+        box.step(CPU_CYCLES)
         g, _, _, _ = box.get_state_numpy()
         box.close()
         e = {}

@@ -392,6 +392,7 @@ stage_kernel(BatchArgs ba) {
   SA_t& SA = *reinterpret_cast<SA_t*>(smem_raw);
   auto& S = SA.s;
   constexpr bool CL = Carry<R, TX, TY>::in_lds;
+  constexpr bool PF = sizeof(R) == 4 && RECON != RECON_PPM;  // next-plane prefetch (below)
 
   // XCD-aware order: the hardware deals blocks round-robin over 8 XCDs; give
   // each XCD a contiguous run of spatially adjacent tiles so halos hit its L2.
@@ -534,6 +535,19 @@ stage_kernel(BatchArgs ba) {
 
   for (int m = z0 - 1; m <= z1; ++m) {
     const int km = wrapi(m, a.nz);
+    // FP32: the next plane's state (and halo item) is loaded before the face
+    // solves, so its memory latency overlaps them (src is never written by this
+    // launch); FP64 and FP32 PPM have no registers to spare for it (measured:
+    // the spills cost more than the latency)
+    Raw<R> rnext, rxnext;
+    if constexpr (PF) {
+      const int kn = wrapi(PPM ? m + 2 : m + 1, a.nz);
+      load_raw<HY>(a, gi, gi1, gj, gj1, kn, wrapi(kn + 1, a.nz), rnext);
+      if (has_extra) {
+        const int kx = wrapi(m + 1, a.nz);
+        load_raw<HY>(a, xgi, xgi1, xgj, xgj1, kx, wrapi(kx + 1, a.nz), rxnext);
+      }
+    }
     // ---------------- A: x- and y-faces of plane m from the LDS plane
     Face<R> fx = {}, fy = {};
     if (do_x || corner_x) {
@@ -631,9 +645,11 @@ stage_kernel(BatchArgs ba) {
     Cell<R> w1;
     Cell<R> w2;  // PPM: plane m+2
     {
-      Raw<R> r;
-      const int kn = wrapi(PPM ? m + 2 : m + 1, a.nz);
-      load_raw<HY>(a, gi, gi1, gj, gj1, kn, wrapi(kn + 1, a.nz), r);
+      Raw<R> r = rnext;
+      if constexpr (!PF) {
+        const int kn = wrapi(PPM ? m + 2 : m + 1, a.nz);
+        load_raw<HY>(a, gi, gi1, gj, gj1, kn, wrapi(kn + 1, a.nz), r);
+      }
       to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1,
               PPM ? w2 : w1);
       if constexpr (PPM) w1 = wn;
@@ -647,9 +663,11 @@ stage_kernel(BatchArgs ba) {
     const R bz_m = HY ? R(0) : gld(a.src[7], (long long)km * plane + col);
     Cell<R> wx;  // halo item of plane m+1
     if (has_extra) {
-      Raw<R> r;
-      const int kn = wrapi(m + 1, a.nz);
-      load_raw<HY>(a, xgi, xgi1, xgj, xgj1, kn, wrapi(kn + 1, a.nz), r);
+      Raw<R> r = rxnext;
+      if constexpr (!PF) {
+        const int kn = wrapi(m + 1, a.nz);
+        load_raw<HY>(a, xgi, xgi1, xgj, xgj1, kn, wrapi(kn + 1, a.nz), r);
+      }
       to_prim(r.rho, r.mx, r.my, r.mz, r.en, r.bxl, r.bxr, r.byl, r.byr, r.bzl, r.bzr, a.gm1, wx);
     }
     Face<R> fz = {};
