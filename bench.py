@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, the same
-# for FP64 and non-packed FP32 (packed FP32 is not used by this build).
+# for FP64 and non-packed FP32 (the kernels are compiled without packed FP32).
 ALU_PEAK_TFLOPS = 78.6
 # Algorithmic floating-point operations (add/sub, mul, div, sqrt) per cell and
 # stage of this method on this 256^3 input with HLLD, counted on the oracle by
@@ -287,8 +287,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 8, "copies": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: the library runs one box on one GPU (asked for --gpus {args.gpus}); "
+              "sharding a box over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
