@@ -42,6 +42,10 @@ def test_workspace_bytes_and_argument_checks():
     assert n64 - 16 * 32 ** 3 * 8 < 1 << 20
     bad = make_params(0, 32, 32)
     assert L.mhd_workspace_bytes(C.byref(bad)) == 0
+    # extents up to 4096 cells per direction
+    assert L.mhd_workspace_bytes(C.byref(make_params(4096, 2, 3))) > 0
+    assert L.mhd_workspace_bytes(C.byref(make_params(4097, 2, 3))) == 0
+    assert L.mhd_workspace_bytes(C.byref(make_params(2, 3, 4097))) == 0
     ctx = C.c_void_p()
     # invalid grid, gamma, cfl: rejected before any device call
     for kw in ({"nx": 0}, {"gamma": 1.0}, {"cfl": 1.0}, {"cfl": 0.0}):

@@ -208,3 +208,16 @@ def test_sedov_hllc_fp32_within_tolerance():
     err = max_rel(g, o)  # the field group is exactly zero on both sides
     print("sedov hllc fp32 max rel", err)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("dims", [(4096, 2, 3), (3, 4096, 2), (2, 3, 4096)])
+def test_maximum_extent_fp64(dims):
+    """Boxes at the largest extent the ABI accepts (4096 cells) along each axis:
+    many tiles or z-chunks along it, two cycles bit-identical to the oracle."""
+    need_gpu()
+    s = I.turbulence(dims, seed=53, kpeak=8.0, mach=0.8, b0=(0.2, 0.1, -0.1))
+    l = s.pop("_l")
+    print("max extent", dims, flush=True)
+    g, o, gd, od, _ = run_both(s, dims, 2, l=l, per_step=True)
+    assert bit_equal(g, o)
+    assert gd == od
