@@ -118,13 +118,12 @@ __device__ __forceinline__ R ppm_interface(R am, R a0, R a1, R a2) {
   return ai;
 }
 
-// face values of cell a2 from the five cells a0 .. a4
+// face values of cell a2 from the five cells a0 .. a4 and its two interface
+// values am (between a1 and a2) and ap (between a2 and a3)
 template <typename R>
-__device__ __forceinline__ void ppm_faces(R a0, R a1, R a2, R a3, R a4, R& lo, R& hi) {
+__device__ __forceinline__ void ppm_limit(R a0, R a1, R a2, R a3, R a4, R am, R ap, R& lo, R& hi) {
   const R C = R(1.25);
   const R aj = a2;
-  R am = ppm_interface(a0, a1, a2, a3);
-  R ap = ppm_interface(a1, a2, a3, a4);
   if ((ap - aj) * (aj - am) <= R(0) || (a3 - aj) * (aj - a1) <= R(0)) {
     const R d2 = R(-2) * (R(6) * aj - R(3) * (am + ap));
     const R d2c = (a1 - R(2) * aj) + a3;

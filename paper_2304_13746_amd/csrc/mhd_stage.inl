@@ -170,10 +170,14 @@ __device__ __forceinline__ Prim<R> as_prim(const R* q) {
 template <int RECON, int NS, typename R>
 __device__ __forceinline__ void face_states(const R (&q)[NS][7], int v, R& ql, R& qr) {
   if constexpr (RECON == RECON_PPM) {
+    // the interface value at the face itself serves both cells
+    const R i01 = ppm_interface(q[0][v], q[1][v], q[2][v], q[3][v]);
+    const R i12 = ppm_interface(q[1][v], q[2][v], q[3][v], q[4][v]);
+    const R i23 = ppm_interface(q[2][v], q[3][v], q[4][v], q[5][v]);
     R lo, hi;
-    ppm_faces(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v], lo, hi);
+    ppm_limit(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v], i01, i12, lo, hi);
     ql = hi;  // upper face of the cell below the face
-    ppm_faces(q[1][v], q[2][v], q[3][v], q[4][v], q[5][v], lo, hi);
+    ppm_limit(q[1][v], q[2][v], q[3][v], q[4][v], q[5][v], i12, i23, lo, hi);
     qr = lo;  // lower face of the cell above it
   } else {
     ql = recon_hi<RECON>(q[0][v], q[1][v], q[2][v]);
@@ -482,6 +486,10 @@ stage_kernel(BatchArgs ba) {
   constexpr bool PPM = RECON == RECON_PPM;
   R zm2[PPM ? 7 : 1];
   Cell<R> wn;
+  // FP64 PPM also carries the interface value at (m-1/2) from one cell to the
+  // next (FP32 PPM has no registers to spare)
+  constexpr bool ZC = PPM && sizeof(R) == 8;
+  R zap[ZC ? 7 : 1];
   // U - tau_x dFx - tau_y dFy of cell m-1 and the z-flux at (m-1)-1/2:
   // registers, or this thread's LDS slots
   R part[5] = {0, 0, 0, 0, 0};
@@ -684,7 +692,14 @@ stage_kernel(BatchArgs ba) {
 #pragma unroll
         for (int v = 0; v < 7; ++v) {
           R lo, hi;
-          ppm_faces(zm2[v], qa[v], qb[v], qc[v], qd[v], lo, hi);
+          R am;
+          if constexpr (ZC)
+            am = m == z0 - 1 ? ppm_interface(zm2[v], qa[v], qb[v], qc[v]) : zap[v];
+          else
+            am = ppm_interface(zm2[v], qa[v], qb[v], qc[v]);
+          const R ap = ppm_interface(qa[v], qb[v], qc[v], qd[v]);
+          ppm_limit(zm2[v], qa[v], qb[v], qc[v], qd[v], am, ap, lo, hi);
+          if constexpr (ZC) zap[v] = ap;
           bot[v] = lo;
           zm2[v] = qa[v];  // plane m-1 becomes the window's far end
           qa[v] = hi;
