@@ -393,8 +393,12 @@ int choose_lz(int tile, int nx, int ny, int nz) {
   int tx, ty;
   tile_dims(tile, &tx, &ty);
   long long tiles = (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
-  // aim for >= 2048 blocks (8 per CU), chunks of at least 16 planes
+  // aim for >= 2048 blocks (8 per CU) with a number of z-chunks that is a
+  // multiple of the 8 XCDs, so that the XCD-aware block order gives each XCD
+  // whole z-slabs (measured at 256^3: 7% (FP64) and 3% (FP32) faster than 6
+  // chunks; at 512^3 FP32 up to 13%); chunks of at least 16 planes
   long long want = (2048 + tiles - 1) / tiles;
+  want = (want + 7) / 8 * 8;
   int lz = (int)((nz + want - 1) / want);
   if (lz < 16) lz = 16;
   if (lz > nz) lz = nz;
