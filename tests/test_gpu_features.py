@@ -28,6 +28,21 @@ def test_full_size_256_fp64_bit_exact(turb256):
     assert gd == od and tg == to
 
 
+@pytest.mark.parametrize("opts", [
+    {"integrator": "rk3"}, {"recon": "limo3", "integrator": "rk3"},
+    {"recon": "ppm", "integrator": "rk3"}, {"emf": "e0"}, {"emf": "arith"}, {"emf": "uct_hll"},
+    {"riemann": "hll"}], ids=lambda o: "-".join(o.values()))
+def test_full_size_256_options_fp64_bit_exact(turb256, opts):
+    """Each scheme option the benchmark times, on the same 256^3 input and in
+    the same default launch shape, one cycle: bit-identical to the oracle with
+    that option, including the next dt."""
+    need_gpu()
+    print("256^3 option", opts, flush=True)
+    g, o, gd, od, (tg, to) = run_both(turb256, (256, 256, 256), 1, **opts)
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+
+
 def test_full_size_256_fp32(turb256):
     """One FP32 cycle at 256^3 against the FP64 oracle on the rounded input:
     1e-5 norm-wise relative, face fields near E^c upwind ties to the looser
