@@ -328,11 +328,41 @@ struct SmemHydro {
   R ycons[5][T::NE], ycmax[T::NE];
 };
 
-template <typename R, int TX, int TY, bool HY, int H>
+// PPM face values limited once per cell (the FP64 PPM path): the upper x- and
+// y-face values of every column and ring corner, and the lower faces of the two
+// ring corners whose faces the tile solves.
+template <typename R, int TX, int TY>
+struct SmemPPM {
+  static constexpr int NE = Tile<TX, TY, 3>::NE;
+  R xhi[7][NE], yhi[7][NE];
+  R xlo_c[7], ylo_c[7];  // lower x-face of (TX, -1), lower y-face of (-1, TY)
+};
+struct NoSmem {};
+
+template <typename R, int TX, int TY, bool HY, int H, bool DD = false>
 struct SmemAll {
   std::conditional_t<HY, SmemHydro<R, TX, TY, H>, Smem<R, TX, TY, H>> s;
   Carry<R, TX, TY> c;
+  std::conditional_t<DD, SmemPPM<R, TX, TY>, NoSmem> p;
 };
+
+// Face-frame variable v of direction D (0: x, 1: y) of LDS cell iw, for a
+// runtime v: x-frame (rho, vx, vy, vz, by, bz, p), y-frame (rho, vy, vz, vx, bz,
+// bx, p); the hydrodynamic plane holds no field.
+template <bool HY, int D, typename SM>
+__device__ __forceinline__ auto lds_frame_var(const SM& S, int v, int iw) {
+  using R = std::remove_cv_t<std::remove_reference_t<decltype(S.w[0][0])>>;
+  int f;
+  if constexpr (D == 0)
+    f = v < 4 ? v : v + 1;
+  else
+    f = v == 0 ? 0 : v == 1 ? 2 : v == 2 ? 3 : v == 3 ? 1 : v == 4 ? 6 : v == 5 ? 4 : 7;
+  if constexpr (HY) {
+    if (v == 4 || v == 5) return R(0);
+    if (v == 6) f = 4;
+  }
+  return S.w[f][iw];
+}
 
 // Primitive plane entries in LDS (the hydrodynamic layout keeps no field).
 template <bool HY, typename SM, typename R>
@@ -392,7 +422,11 @@ stage_kernel(BatchArgs ba) {
   // and solves only the faces the tile's own cells need (it leaves B alone)
   constexpr bool UCT = EMF == EMF_UCT;
   constexpr bool NE = HY || UCT;
-  using SA_t = SmemAll<R, TX, TY, HY, H>;
+  // FP64 PPM limits each cell's x and y faces once per plane into LDS (FP32 PPM
+  // limits them per face: the extra 15 KB of LDS would cost it a block per CU,
+  // measured 20 % slower)
+  constexpr bool DD = RECON == RECON_PPM && sizeof(R) == 8;
+  using SA_t = SmemAll<R, TX, TY, HY, H, DD>;
   SA_t& SA = *reinterpret_cast<SA_t*>(smem_raw);
   auto& S = SA.s;
   constexpr bool CL = Carry<R, TX, TY>::in_lds;
@@ -556,21 +590,94 @@ stage_kernel(BatchArgs ba) {
         load_raw<HY>(a, xgi, xgi1, xgj, xgj1, kx, wrapi(kx + 1, a.nz), rxnext);
       }
     }
+    // ---------------- A0 (FP64 PPM): the x and y face values of every cell once
+    R xlo[DD ? 7 : 1], ylo[DD ? 7 : 1];
+    if constexpr (DD) {
+      auto& P = SA.p;
+      {
+        R q[5][7];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+          Cell<R> c;
+          get_cell<HY>(S, T::w(ci - 2 + s, cj), c);
+          frame_vals<0>(c, q[s]);
+        }
+#pragma unroll
+        for (int v = 0; v < 7; ++v) {
+          R lo, hi;
+          ppm_limit(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v],
+                    ppm_interface(q[0][v], q[1][v], q[2][v], q[3][v]),
+                    ppm_interface(q[1][v], q[2][v], q[3][v], q[4][v]), lo, hi);
+          P.xhi[v][ex_me] = hi;
+          xlo[v] = lo;
+        }
+      }
+      {
+        R q[5][7];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+          Cell<R> c;
+          get_cell<HY>(S, T::w(ci, cj - 2 + s), c);
+          frame_vals<1>(c, q[s]);
+        }
+#pragma unroll
+        for (int v = 0; v < 7; ++v) {
+          R lo, hi;
+          ppm_limit(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v],
+                    ppm_interface(q[0][v], q[1][v], q[2][v], q[3][v]),
+                    ppm_interface(q[1][v], q[2][v], q[3][v], q[4][v]), lo, hi);
+          P.yhi[v][ex_me] = hi;
+          ylo[v] = lo;
+        }
+      }
+      // the ring corners (-1, -1), (TX, -1), (-1, TY) are nobody's column: one
+      // lane per (corner, direction, variable), so no wave does a second cell
+      if (t < 42) {
+        const int cc = t / 14, d = (t / 7) % 2, v = t % 7;
+        const int cx = cc == 1 ? TX : -1, cy = cc == 2 ? TY : -1;
+        R a[5];
+#pragma unroll
+        for (int s = 0; s < 5; ++s)
+          a[s] = d == 0 ? lds_frame_var<HY, 0>(S, v, T::w(cx - 2 + s, cy))
+                        : lds_frame_var<HY, 1>(S, v, T::w(cx, cy - 2 + s));
+        R lo, hi;
+        ppm_limit(a[0], a[1], a[2], a[3], a[4], ppm_interface(a[0], a[1], a[2], a[3]),
+                  ppm_interface(a[1], a[2], a[3], a[4]), lo, hi);
+        const int ec = T::e(cx, cy);
+        if (d == 0) {
+          P.xhi[v][ec] = hi;
+          if (cc == 1) P.xlo_c[v] = lo;
+        } else {
+          P.yhi[v][ec] = hi;
+          if (cc == 2) P.ylo_c[v] = lo;
+        }
+      }
+      __syncthreads();
+    }
     // ---------------- A: x- and y-faces of plane m from the LDS plane
     Face<R> fx = {}, fy = {};
     if (do_x || corner_x) {
       const int fi = corner_x ? TX : ci, fj = corner_x ? -1 : cj;
-      R q[NS][7];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        Cell<R> c;
-        const int iw = T::w(fi - NS / 2 + s, fj);
-        get_cell<HY>(S, iw, c);
-        frame_vals<0>(c, q[s]);
-      }
       R ql[7], qr[7];
+      if constexpr (DD) {
+        const int el = T::e(fi - 1, fj);
 #pragma unroll
-      for (int v = 0; v < 7; ++v) face_states<RECON>(q, v, ql[v], qr[v]);
+        for (int v = 0; v < 7; ++v) {
+          ql[v] = SA.p.xhi[v][el];
+          qr[v] = corner_x ? SA.p.xlo_c[v] : xlo[v];
+        }
+      } else {
+        R q[NS][7];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          Cell<R> c;
+          const int iw = T::w(fi - NS / 2 + s, fj);
+          get_cell<HY>(S, iw, c);
+          frame_vals<0>(c, q[s]);
+        }
+#pragma unroll
+        for (int v = 0; v < 7; ++v) face_states<RECON>(q, v, ql[v], qr[v]);
+      }
       R bn = R(0);
       if constexpr (!HY) {
         if (corner_x) {
@@ -604,17 +711,26 @@ stage_kernel(BatchArgs ba) {
     }
     if (do_y || corner_y) {
       const int fi = corner_y ? -1 : ci, fj = corner_y ? TY : cj;
-      R q[NS][7];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        Cell<R> c;
-        const int iw = T::w(fi, fj - NS / 2 + s);
-        get_cell<HY>(S, iw, c);
-        frame_vals<1>(c, q[s]);
-      }
       R ql[7], qr[7];
+      if constexpr (DD) {
+        const int el = T::e(fi, fj - 1);
 #pragma unroll
-      for (int v = 0; v < 7; ++v) face_states<RECON>(q, v, ql[v], qr[v]);
+        for (int v = 0; v < 7; ++v) {
+          ql[v] = SA.p.yhi[v][el];
+          qr[v] = corner_y ? SA.p.ylo_c[v] : ylo[v];
+        }
+      } else {
+        R q[NS][7];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          Cell<R> c;
+          const int iw = T::w(fi, fj - NS / 2 + s);
+          get_cell<HY>(S, iw, c);
+          frame_vals<1>(c, q[s]);
+        }
+#pragma unroll
+        for (int v = 0; v < 7; ++v) face_states<RECON>(q, v, ql[v], qr[v]);
+      }
       R bn = R(0);
       if constexpr (!HY) {
         if (corner_y) {
@@ -900,7 +1016,8 @@ template <typename R, int SOLVER, int RECON, int EMF, int CT, int MODE, int TX, 
 static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) {
   using T = Tile<TX, TY>;
   const size_t lds =
-      sizeof(SmemAll<R, TX, TY, SOLVER == SOLVER_HLLC, RECON == RECON_PPM ? 3 : 2>);
+      sizeof(SmemAll<R, TX, TY, SOLVER == SOLVER_HLLC, RECON == RECON_PPM ? 3 : 2,
+                     RECON == RECON_PPM && sizeof(R) == 8>);
   auto fn = stage_kernel<R, SOLVER, RECON, EMF, CT, MODE, TX, TY>;
   if (prepare)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
