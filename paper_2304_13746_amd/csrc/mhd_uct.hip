@@ -15,7 +15,7 @@
 //              either side), with the larger speeds of the two Q-faces that
 //              share the edge; F_P likewise along P from the two Q-faces:
 //                F = (a+ vL bL + a- vR bR - a+ a- (bR - bL)) / (a+ + a-);
-//   k_uct_ct:  B_dst = w ((B_src - dt curl E)) + w0 B_base by Stokes' theorem
+//   k_uct_ct:  B_dst = w (B_src - dt curl E) + w0 B_base by Stokes' theorem
 //              on each face (B_dst = B_src - dt curl E for a first stage).
 // Both are one thread per cell over plain SoA arrays; the update is its own
 // launch because it reads the EMFs of neighbouring cells.  Expressions are
