@@ -61,8 +61,9 @@ typedef enum { MHD_HLLD = 0, MHD_HLL = 1, MHD_HLLC = 2 } mhd_riemann;
  * UCT-HLL, a 2D HLL Riemann solve at each edge (Londrillo & Del Zanna 2004, in
  * the form of Mignone & Del Zanna 2021), which splits each edge EMF into two 1D
  * HLL fluxes across the edge from the faces' normal fields and HLL-averaged
- * transverse velocities reconstructed to it.  UCT-HLL is built for HLLD/HLL
- * with MHD_PLM and MHD_CT_FACE (else MHD_ERR_UNSUPPORTED); it runs two extra
+ * transverse velocities reconstructed to it (with the cell reconstruction's
+ * limiter).  UCT-HLL is built for HLLD/HLL with MHD_PLM or MHD_LIMO3 and
+ * MHD_CT_FACE (else MHD_ERR_UNSUPPORTED); it runs two extra
  * one-thread-per-cell launches per stage and needs 15 more arrays of one field
  * in the workspace (mhd_workspace_bytes accounts for them). */
 typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2, MHD_EMF_UCT_HLL = 3 } mhd_emf;

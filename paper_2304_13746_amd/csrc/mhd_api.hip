@@ -280,7 +280,8 @@ hipError_t launch_uct(mhd_ctx* const* c, const Roles* r, int n, int mode, double
     }
     ba.start[m] = g;
     ba.total = g;
-    hipError_t e = c[i0]->p.precision == MHD_FP32 ? uct_f32(ba, st) : uct_f64(ba, st);
+    const int rc = c[i0]->p.recon;
+    hipError_t e = c[i0]->p.precision == MHD_FP32 ? uct_f32(ba, rc, st) : uct_f64(ba, rc, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -501,9 +502,9 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH &&
       p->emf != MHD_EMF_UCT_HLL)
     return MHD_ERR_UNSUPPORTED;
-  // UCT-HLL is built for the MHD solvers with PLM and face-field CT
+  // UCT-HLL is built for the MHD solvers with PLM or LimO3 and face-field CT
   if (p->emf == MHD_EMF_UCT_HLL &&
-      (p->riemann == MHD_HLLC || p->recon != MHD_PLM || p->ct != MHD_CT_FACE))
+      (p->riemann == MHD_HLLC || p->recon == MHD_PPM || p->ct != MHD_CT_FACE))
     return MHD_ERR_UNSUPPORTED;
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3 && p->recon != MHD_PPM)
     return MHD_ERR_UNSUPPORTED;

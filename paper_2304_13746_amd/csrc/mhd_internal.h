@@ -104,8 +104,8 @@ hipError_t vpot_curl_f64(const BatchArgs& b, hipStream_t st);
 // w0 B_base.  ba.start[] counts blocks of kUctBlock cells.
 constexpr int kUctBlock = 256;
 constexpr int kUctArrays = 15;
-hipError_t uct_f64(const BatchArgs& b, hipStream_t st);
-hipError_t uct_f32(const BatchArgs& b, hipStream_t st);
+hipError_t uct_f64(const BatchArgs& b, int recon, hipStream_t st);
+hipError_t uct_f32(const BatchArgs& b, int recon, hipStream_t st);
 hipError_t stage_f32(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
                      bool prepare);
 int tile_dims(int tile, int* tx, int* ty);

@@ -1045,8 +1045,8 @@ static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) 
     return hipErrorInvalidValue;
   }
   if (ba.emf == EMF_UCT) {
-    // UCT-HLL is built with PLM and the face-field form
-    if constexpr (RECON == RECON_PLM) {
+    // UCT-HLL is built with PLM or LimO3 and the face-field form
+    if constexpr (RECON == RECON_PLM || RECON == RECON_LIMO3) {
       if (ba.ct == CT_FACE) return launch_mode<R, SOLVER, RECON, EMF_UCT, CT_FACE, TX, TY>(ba, st, prepare);
     }
     return hipErrorInvalidValue;

@@ -11,8 +11,9 @@
 //                E_e = F_Q - F_P,
 //              F_Q the 1D HLL flux of v_Q B_P across the edge along Q, from
 //              the two P-faces that meet there (their normal field B_P and
-//              averaged v_Q, van Leer-reconstructed along Q to the edge from
-//              either side), with the larger speeds of the two Q-faces that
+//              averaged v_Q, reconstructed along Q to the edge from either
+//              side with the cell limiter, van Leer or LimO3), with the larger
+//              speeds of the two Q-faces that
 //              share the edge; F_P likewise along P from the two Q-faces:
 //                F = (a+ vL bL + a- vR bR - a+ a- (bR - bL)) / (a+ + a-);
 //   k_uct_ct:  B_dst = w (B_src - dt curl E) + w0 B_base by Stokes' theorem
@@ -55,7 +56,7 @@ __device__ __forceinline__ R uct_part(R ap, R am, R vl, R bl, R vr, R br) {
 
 // the 1D HLL flux across one edge from four face values of b and v along the
 // line through it (indices o[0..3]) and the speeds of the faces it crosses
-template <typename R>
+template <int RECON, typename R>
 __device__ __forceinline__ R edge_flux(const R* b, const R* v, const long long* o, R ap, R am) {
   R bq[4], vq[4];
 #pragma unroll
@@ -63,14 +64,14 @@ __device__ __forceinline__ R edge_flux(const R* b, const R* v, const long long* 
     bq[q] = ld(b, o[q]);
     vq[q] = ld(v, o[q]);
   }
-  const R bl = recon_hi<RECON_PLM>(bq[0], bq[1], bq[2]);
-  const R br = recon_lo<RECON_PLM>(bq[1], bq[2], bq[3]);
-  const R vl = recon_hi<RECON_PLM>(vq[0], vq[1], vq[2]);
-  const R vr = recon_lo<RECON_PLM>(vq[1], vq[2], vq[3]);
+  const R bl = recon_hi<RECON>(bq[0], bq[1], bq[2]);
+  const R br = recon_lo<RECON>(bq[1], bq[2], bq[3]);
+  const R vl = recon_hi<RECON>(vq[0], vq[1], vq[2]);
+  const R vr = recon_lo<RECON>(vq[1], vq[2], vq[3]);
   return uct_part(ap, am, vl, bl, vr, br);
 }
 
-template <typename R>
+template <typename R, int RECON>
 __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   const int box = box_of(ba, blockIdx.x);
   const BoxDesc* d = ba.desc[box];
@@ -97,10 +98,10 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   {
     const long long cjm = yj(-1), cim = xi(-1);
     for (int q = 0; q < 4; ++q) o[q] = xi(q - 2);  // y-faces (i-2 .. i+1, j-1/2)
-    const R fp = edge_flux(by, fa(1, U_VT2), o, rmax(ld(fa(0, U_AP), cjm), ld(fa(0, U_AP), c)),
+    const R fp = edge_flux<RECON>(by, fa(1, U_VT2), o, rmax(ld(fa(0, U_AP), cjm), ld(fa(0, U_AP), c)),
                            rmax(ld(fa(0, U_AM), cjm), ld(fa(0, U_AM), c)));
     for (int q = 0; q < 4; ++q) o[q] = yj(q - 2);  // x-faces (i-1/2, j-2 .. j+1)
-    const R fq = edge_flux(bx, fa(0, U_VT1), o, rmax(ld(fa(1, U_AP), cim), ld(fa(1, U_AP), c)),
+    const R fq = edge_flux<RECON>(bx, fa(0, U_VT1), o, rmax(ld(fa(1, U_AP), cim), ld(fa(1, U_AP), c)),
                            rmax(ld(fa(1, U_AM), cim), ld(fa(1, U_AM), c)));
     u[(U_E + 2) * us + c] = fq - fp;
   }
@@ -108,10 +109,10 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   {
     const long long ckm = zk(-1), cjm = yj(-1);
     for (int q = 0; q < 4; ++q) o[q] = yj(q - 2);  // z-faces (i, j-2 .. j+1, k-1/2)
-    const R fp = edge_flux(bz, fa(2, U_VT2), o, rmax(ld(fa(1, U_AP), ckm), ld(fa(1, U_AP), c)),
+    const R fp = edge_flux<RECON>(bz, fa(2, U_VT2), o, rmax(ld(fa(1, U_AP), ckm), ld(fa(1, U_AP), c)),
                            rmax(ld(fa(1, U_AM), ckm), ld(fa(1, U_AM), c)));
     for (int q = 0; q < 4; ++q) o[q] = zk(q - 2);  // y-faces (i, j-1/2, k-2 .. k+1)
-    const R fq = edge_flux(by, fa(1, U_VT1), o, rmax(ld(fa(2, U_AP), cjm), ld(fa(2, U_AP), c)),
+    const R fq = edge_flux<RECON>(by, fa(1, U_VT1), o, rmax(ld(fa(2, U_AP), cjm), ld(fa(2, U_AP), c)),
                            rmax(ld(fa(2, U_AM), cjm), ld(fa(2, U_AM), c)));
     u[U_E * us + c] = fq - fp;
   }
@@ -119,10 +120,10 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   {
     const long long cim = xi(-1), ckm = zk(-1);
     for (int q = 0; q < 4; ++q) o[q] = zk(q - 2);  // x-faces (i-1/2, j, k-2 .. k+1)
-    const R fp = edge_flux(bx, fa(0, U_VT2), o, rmax(ld(fa(2, U_AP), cim), ld(fa(2, U_AP), c)),
+    const R fp = edge_flux<RECON>(bx, fa(0, U_VT2), o, rmax(ld(fa(2, U_AP), cim), ld(fa(2, U_AP), c)),
                            rmax(ld(fa(2, U_AM), cim), ld(fa(2, U_AM), c)));
     for (int q = 0; q < 4; ++q) o[q] = xi(q - 2);  // z-faces (i-2 .. i+1, j, k-1/2)
-    const R fq = edge_flux(bz, fa(2, U_VT1), o, rmax(ld(fa(0, U_AP), ckm), ld(fa(0, U_AP), c)),
+    const R fq = edge_flux<RECON>(bz, fa(2, U_VT1), o, rmax(ld(fa(0, U_AP), ckm), ld(fa(0, U_AP), c)),
                            rmax(ld(fa(0, U_AM), ckm), ld(fa(0, U_AM), c)));
     u[(U_E + 1) * us + c] = fq - fp;
   }
@@ -173,9 +174,13 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_ct(BatchArgs ba) {
 }
 
 template <typename R>
-hipError_t uct_launch(const BatchArgs& ba, hipStream_t st) {
+hipError_t uct_launch(const BatchArgs& ba, int recon, hipStream_t st) {
   if (ba.nbox < 1 || ba.nbox > kMaxBatch || ba.total < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_uct_emf<R>, dim3(ba.total), dim3(kUctBlock), 0, st, ba);
+  if (recon != RECON_PLM && recon != RECON_LIMO3) return hipErrorInvalidValue;
+  if (recon == RECON_LIMO3)
+    hipLaunchKernelGGL((k_uct_emf<R, RECON_LIMO3>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
+  else
+    hipLaunchKernelGGL((k_uct_emf<R, RECON_PLM>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_uct_ct<R>, dim3(ba.total), dim3(kUctBlock), 0, st, ba);
@@ -184,7 +189,11 @@ hipError_t uct_launch(const BatchArgs& ba, hipStream_t st) {
 
 }  // namespace
 
-hipError_t uct_f64(const BatchArgs& ba, hipStream_t st) { return uct_launch<double>(ba, st); }
-hipError_t uct_f32(const BatchArgs& ba, hipStream_t st) { return uct_launch<float>(ba, st); }
+hipError_t uct_f64(const BatchArgs& ba, int recon, hipStream_t st) {
+  return uct_launch<double>(ba, recon, st);
+}
+hipError_t uct_f32(const BatchArgs& ba, int recon, hipStream_t st) {
+  return uct_launch<float>(ba, recon, st);
+}
 
 }  // namespace mhd

@@ -138,3 +138,24 @@ def test_graph_replay_matches_alone(scheme):
         a, ta, da, _ = alone.get_state_numpy()
         g, t, dt, _ = bx.get_state_numpy()
         assert bit_equal(a, g) and ta == t and da == dt, sp["dims"]
+
+
+def test_uct_with_limo3():
+    """UCT-HLL with LimO3 (the edge values reconstructed with the same limiter)
+    and RK3: FP64 bit-identical, FP32 within 1e-5."""
+    need_gpu()
+    dims = (40, 24, 18)
+    s = I.turbulence(dims, seed=47, kpeak=2.0, mach=1.0, b0=(0.2, 0.25, -0.15))
+    l = s.pop("_l")
+    print("uct limo3 fp64", flush=True)
+    g, o, gd, od, _ = run_both(s, dims, 4, l=l, integrator="rk3", per_step=True, emf="uct_hll",
+                               recon="limo3")
+    assert bit_equal(g, o)
+    assert gd == od
+    print("uct limo3 fp32", flush=True)
+    s32 = I.to_float32_exact(I.orszag_tang(32))
+    g, o, _, _, _ = run_both(s32, (32, 32, 32), 5, precision="fp32", integrator="rk3",
+                             emf="uct_hll", recon="limo3")
+    err = max_rel(g, o)
+    print("uct limo3 fp32 max rel", err)
+    assert err <= 1e-5
