@@ -70,8 +70,8 @@ typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2, MHD_EMF_UCT_HL
 /* Reconstructions of Sec. 2.3, all on the primitives: van Leer PLM (default),
  * the compact third-order LimO3 limiter (Cada & Torrilhon 2009), and PPM
  * (Colella & Woodward 1984) with the extremum-preserving limiter of Colella &
- * Sekora (2008).  PPM reads three cells each way and is built with
- * MHD_CT_FACE and, for HLLD/HLL, MHD_EMF_EC (else MHD_ERR_UNSUPPORTED). */
+ * Sekora (2008).  PPM reads three cells each way; it combines with every EMF
+ * scheme but UCT-HLL and with both CT forms. */
 typedef enum { MHD_PLM = 0, MHD_LIMO3 = 1, MHD_PPM = 2 } mhd_recon;
 /* Constrained transport (Sec. 2.4): the face field updated by the discrete
  * Stokes theorem, or carried by an edge vector potential A (eqs. ind_vec:

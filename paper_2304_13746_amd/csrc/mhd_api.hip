@@ -508,10 +508,6 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
     return MHD_ERR_UNSUPPORTED;
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3 && p->recon != MHD_PPM)
     return MHD_ERR_UNSUPPORTED;
-  // PPM is built with face-field CT and, for the MHD solvers, the E^c scheme
-  if (p->recon == MHD_PPM &&
-      (p->ct != MHD_CT_FACE || (p->riemann != MHD_HLLC && p->emf != MHD_EMF_EC)))
-    return MHD_ERR_UNSUPPORTED;
   if (p->ct != MHD_CT_FACE && p->ct != MHD_CT_VECPOT) return MHD_ERR_INVALID_ARG;
   if (p->ct == MHD_CT_VECPOT &&
       (p->precision != MHD_FP64 || p->emf != MHD_EMF_EC || p->riemann == MHD_HLLC))

@@ -1057,13 +1057,16 @@ static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) 
   return launch_mode<R, SOLVER, RECON, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
 }
 
-// PPM is built with the default EMF scheme and the face-field form of CT only.
 template <typename R, int SOLVER, int TX, int TY>
 static hipError_t launch_recon(const BatchArgs& ba, int recon, hipStream_t st, bool prepare) {
   constexpr bool HY = SOLVER == SOLVER_HLLC;
   if (recon == RECON_PPM) {
-    if (ba.ct != CT_FACE || (!HY && ba.emf != EMF_EC)) return hipErrorInvalidValue;
-    return launch_mode<R, SOLVER, RECON_PPM, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
+    if constexpr (HY) {
+      if (ba.ct != CT_FACE) return hipErrorInvalidValue;
+      return launch_mode<R, SOLVER, RECON_PPM, EMF_EC, CT_FACE, TX, TY>(ba, st, prepare);
+    } else {
+      return launch_emf<R, SOLVER, RECON_PPM, TX, TY>(ba, st, prepare);
+    }
   }
   const bool lim = recon == RECON_LIMO3;
   if constexpr (HY) {

@@ -138,11 +138,23 @@ def test_ppm_sedov_hllc_fp32():
         assert not g[f].any()
 
 
-def test_ppm_unsupported_combinations_rejected():
-    """PPM is built with face-field CT and, for HLLD/HLL, the E^c scheme only:
-    other combinations are refused at creation, not run."""
+@pytest.mark.parametrize("emf", ["e0", "arith"])
+def test_ppm_other_emf_schemes_fp64_bit_exact(emf):
+    need_gpu()
+    dims = (37, 29, 11)
+    s = I.turbulence(dims, seed=59, kpeak=2.0, mach=0.9, b0=(0.15, -0.2, 0.25))
+    l = s.pop("_l")
+    print("ppm emf", emf, flush=True)
+    g, o, gd, od, _ = run_both(s, dims, 3, l=l, per_step=True, recon="ppm", emf=emf,
+                               integrator="rk3")
+    assert bit_equal(g, o)
+    assert gd == od
+
+
+def test_ppm_with_uct_rejected():
+    """The UCT-HLL edge solve reconstructs with three-point limiters only: PPM
+    with it is refused at creation, not run."""
     need_gpu()
     from paper_2304_13746_amd.box import MHDBox
-    for kw in ({"emf": "e0"}, {"emf": "arith"}, {"ct": "vecpot"}):
-        with pytest.raises(RuntimeError):
-            MHDBox(16, 16, 16, recon="ppm", **kw)
+    with pytest.raises(RuntimeError):
+        MHDBox(16, 16, 16, recon="ppm", emf="uct_hll")
