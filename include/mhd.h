@@ -62,8 +62,8 @@ typedef enum { MHD_HLLD = 0, MHD_HLL = 1, MHD_HLLC = 2 } mhd_riemann;
  * the form of Mignone & Del Zanna 2021), which splits each edge EMF into two 1D
  * HLL fluxes across the edge from the faces' normal fields and HLL-averaged
  * transverse velocities reconstructed to it (with the cell reconstruction's
- * limiter).  UCT-HLL is built for HLLD/HLL with MHD_PLM or MHD_LIMO3 and
- * MHD_CT_FACE (else MHD_ERR_UNSUPPORTED); it runs two extra
+ * limiter).  UCT-HLL is built for HLLD/HLL with MHD_PLM or MHD_LIMO3 and either
+ * CT form (else MHD_ERR_UNSUPPORTED); it runs two extra
  * one-thread-per-cell launches per stage and needs 15 more arrays of one field
  * in the workspace (mhd_workspace_bytes accounts for them). */
 typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2, MHD_EMF_UCT_HLL = 3 } mhd_emf;
@@ -76,7 +76,7 @@ typedef enum { MHD_PLM = 0, MHD_LIMO3 = 1, MHD_PPM = 2 } mhd_recon;
 /* Constrained transport (Sec. 2.4): the face field updated by the discrete
  * Stokes theorem, or carried by an edge vector potential A (eqs. ind_vec:
  * dA/dt = -E, B = b0 + curl A, b0 the uniform mean field); the potential form
- * is built for FP64 with the E^c scheme and HLLD/HLL. */
+ * is built for FP64 with the E^c or UCT-HLL scheme and HLLD/HLL. */
 typedef enum { MHD_CT_FACE = 0, MHD_CT_VECPOT = 1 } mhd_ct;
 typedef enum { MHD_RK2 = 0, MHD_EULER = 1, MHD_RK3 = 2 } mhd_integrator; /* Tab. weights */
 

@@ -261,7 +261,7 @@ hipError_t launch_stage(mhd_ctx* const* c, const Roles* r, int n, int mode, doub
 // UCT-HLL after a stage launch (mode 0: first stage, 1: combining stage): the
 // edge EMFs from the exported face data, then the face-field update.
 hipError_t launch_uct(mhd_ctx* const* c, const Roles* r, int n, int mode, double w, double w0,
-                      hipStream_t st) {
+                      bool update_b, hipStream_t st) {
   for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
     const int m = n - i0 < kMaxBatch ? n - i0 : kMaxBatch;
     BatchArgs ba = {};
@@ -281,7 +281,8 @@ hipError_t launch_uct(mhd_ctx* const* c, const Roles* r, int n, int mode, double
     ba.start[m] = g;
     ba.total = g;
     const int rc = c[i0]->p.recon;
-    hipError_t e = c[i0]->p.precision == MHD_FP32 ? uct_f32(ba, rc, st) : uct_f64(ba, rc, st);
+    hipError_t e = c[i0]->p.precision == MHD_FP32 ? uct_f32(ba, rc, update_b, st)
+                                                  : uct_f64(ba, rc, update_b, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -299,6 +300,7 @@ hipError_t launch_vpot(mhd_ctx* const* c, const Roles* r, int n, int mode, doubl
     ba.mode = mode;
     ba.w = w;
     ba.w0 = w0;
+    ba.emf = c[i0]->p.emf;
     int g = 0;
     for (int i = 0; i < m; ++i) {
       ba.desc[i] = c[i0 + i]->desc;
@@ -367,7 +369,7 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
     // (same roles and weights)
     auto stage = [&](int mode, double w, double w0) -> bool {
       if (launch_stage(act, roles, m, mode, w, w0, st) != hipSuccess) return false;
-      if (uct && launch_uct(act, roles, m, mode, w, w0, st) != hipSuccess) return false;
+      if (uct && launch_uct(act, roles, m, mode, w, w0, !vp, st) != hipSuccess) return false;
       return !vp || launch_vpot(act, roles, m, mode, w, w0, true, st) == hipSuccess;
     };
     if (!stage(0, 1.0, 0.0)) return MHD_ERR_HIP;
@@ -502,15 +504,16 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH &&
       p->emf != MHD_EMF_UCT_HLL)
     return MHD_ERR_UNSUPPORTED;
-  // UCT-HLL is built for the MHD solvers with PLM or LimO3 and face-field CT
-  if (p->emf == MHD_EMF_UCT_HLL &&
-      (p->riemann == MHD_HLLC || p->recon == MHD_PPM || p->ct != MHD_CT_FACE))
+  // UCT-HLL is built for the MHD solvers with PLM or LimO3 (with the potential
+  // form under its FP64 rule below)
+  if (p->emf == MHD_EMF_UCT_HLL && (p->riemann == MHD_HLLC || p->recon == MHD_PPM))
     return MHD_ERR_UNSUPPORTED;
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3 && p->recon != MHD_PPM)
     return MHD_ERR_UNSUPPORTED;
   if (p->ct != MHD_CT_FACE && p->ct != MHD_CT_VECPOT) return MHD_ERR_INVALID_ARG;
   if (p->ct == MHD_CT_VECPOT &&
-      (p->precision != MHD_FP64 || p->emf != MHD_EMF_EC || p->riemann == MHD_HLLC))
+      (p->precision != MHD_FP64 || (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_UCT_HLL) ||
+       p->riemann == MHD_HLLC))
     return MHD_ERR_UNSUPPORTED;
   if (p->integrator != MHD_RK2 && p->integrator != MHD_EULER && p->integrator != MHD_RK3)
     return MHD_ERR_INVALID_ARG;

@@ -94,8 +94,9 @@ struct BatchArgs {
 hipError_t stage_f64(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
                      bool prepare);
 // vector-potential form (FP64): A_dst = w (A_src - dt E) + w0 A_base on every
-// edge, with E left in the output's face-field slots by the stage kernel, then
-// B_dst = b0 + curl A_dst.  ba.start[] counts blocks of kVpotBlock cells.
+// edge, with E left in the output's face-field slots by the stage kernel (with
+// UCT-HLL, ba.emf == 3, in the edge-EMF scratch arrays), then B_dst = b0 + curl
+// A_dst.  ba.start[] counts blocks of kVpotBlock cells.
 constexpr int kVpotBlock = 256;
 hipError_t vpot_update_f64(const BatchArgs& b, hipStream_t st);
 hipError_t vpot_curl_f64(const BatchArgs& b, hipStream_t st);
@@ -104,8 +105,9 @@ hipError_t vpot_curl_f64(const BatchArgs& b, hipStream_t st);
 // w0 B_base.  ba.start[] counts blocks of kUctBlock cells.
 constexpr int kUctBlock = 256;
 constexpr int kUctArrays = 15;
-hipError_t uct_f64(const BatchArgs& b, int recon, hipStream_t st);
-hipError_t uct_f32(const BatchArgs& b, int recon, hipStream_t st);
+// (with update_b = false only the edge EMFs: the potential form takes them)
+hipError_t uct_f64(const BatchArgs& b, int recon, bool update_b, hipStream_t st);
+hipError_t uct_f32(const BatchArgs& b, int recon, bool update_b, hipStream_t st);
 hipError_t stage_f32(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
                      bool prepare);
 int tile_dims(int tile, int* tx, int* ty);

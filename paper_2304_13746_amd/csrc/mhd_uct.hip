@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_ct(BatchArgs ba) {
 }
 
 template <typename R>
-hipError_t uct_launch(const BatchArgs& ba, int recon, hipStream_t st) {
+hipError_t uct_launch(const BatchArgs& ba, int recon, bool update_b, hipStream_t st) {
   if (ba.nbox < 1 || ba.nbox > kMaxBatch || ba.total < 1) return hipErrorInvalidValue;
   if (recon != RECON_PLM && recon != RECON_LIMO3) return hipErrorInvalidValue;
   if (recon == RECON_LIMO3)
@@ -182,18 +182,18 @@ hipError_t uct_launch(const BatchArgs& ba, int recon, hipStream_t st) {
   else
     hipLaunchKernelGGL((k_uct_emf<R, RECON_PLM>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !update_b) return e;
   hipLaunchKernelGGL(k_uct_ct<R>, dim3(ba.total), dim3(kUctBlock), 0, st, ba);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t uct_f64(const BatchArgs& ba, int recon, hipStream_t st) {
-  return uct_launch<double>(ba, recon, st);
+hipError_t uct_f64(const BatchArgs& ba, int recon, bool update_b, hipStream_t st) {
+  return uct_launch<double>(ba, recon, update_b, st);
 }
-hipError_t uct_f32(const BatchArgs& ba, int recon, hipStream_t st) {
-  return uct_launch<float>(ba, recon, st);
+hipError_t uct_f32(const BatchArgs& ba, int recon, bool update_b, hipStream_t st) {
+  return uct_launch<float>(ba, recon, update_b, st);
 }
 
 }  // namespace mhd

@@ -67,12 +67,12 @@ def test_workspace_bytes_and_argument_checks():
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE, kw
     # UCT-HLL: MHD solvers, PLM or LimO3, face-field CT
     for kw in ({"emf": "uct_hll", "riemann": "hllc"}, {"emf": "uct_hll", "recon": "ppm"},
-               {"emf": "uct_hll", "ct": "vecpot"}):
+               {"emf": "uct_hll", "ct": "vecpot", "precision": "fp32"}):
         q = make_params(8, 8, 8, **kw)
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED, kw
     for kw in ({"recon": "ppm"}, {"recon": "ppm", "riemann": "hllc", "emf": "e0"},
                {"emf": "uct_hll"}, {"emf": "uct_hll", "riemann": "hll", "precision": "fp32"},
-               {"emf": "uct_hll", "recon": "limo3"}):
+               {"emf": "uct_hll", "recon": "limo3"}, {"emf": "uct_hll", "ct": "vecpot"}):
         q = make_params(8, 8, 8, **kw)  # accepted up to the (missing) workspace
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE, kw
     # UCT-HLL takes 15 more arrays of one field in the workspace

@@ -16,10 +16,11 @@ def copy_pot(a):
     return {"ax": a["ax"].copy(), "ay": a["ay"].copy(), "az": a["az"].copy(), "b0": a["b0"]}
 
 
-def gpu_run(s, a, dims, l, nsteps, integrator="rk2", riemann="hlld", stream=None, recon="plm"):
+def gpu_run(s, a, dims, l, nsteps, integrator="rk2", riemann="hlld", stream=None, recon="plm",
+            emf="ec"):
     from paper_2304_13746_amd.box import MHDBox
     box = MHDBox(*dims, *l, integrator=integrator, riemann=riemann, ct="vecpot", b0=a["b0"],
-                 stream=stream, recon=recon)
+                 stream=stream, recon=recon, emf=emf)
     st = dict(s)
     st.update({k: a[k] for k in POT})
     box.set_state(st)
@@ -32,19 +33,22 @@ def gpu_run(s, a, dims, l, nsteps, integrator="rk2", riemann="hlld", stream=None
     return g, t, dts
 
 
-@pytest.mark.parametrize("integrator,recon", [("rk2", "plm"), ("rk3", "plm"), ("rk3", "ppm")])
+@pytest.mark.parametrize("integrator,recon,emf", [("rk2", "plm", "ec"), ("rk3", "plm", "ec"),
+                                                  ("rk3", "ppm", "ec"), ("rk2", "plm", "uct_hll"),
+                                                  ("rk3", "limo3", "uct_hll")])
 @pytest.mark.parametrize("riemann", ["hlld", "hll"])
-def test_vecpot_fp64_bit_exact(integrator, riemann, recon):
+def test_vecpot_fp64_bit_exact(integrator, riemann, recon, emf):
     need_gpu()
     n = 24
     s, a = I.orszag_tang_3d(n, potential=True)
     dims, l = (n, n, n), (1.0, 1.0, 1.0)
-    print("vecpot", integrator, riemann, recon, flush=True)
-    g, tg, gd = gpu_run(s, a, dims, l, 5, integrator, riemann, recon=recon)
+    print("vecpot", integrator, riemann, recon, emf, flush=True)
+    g, tg, gd = gpu_run(s, a, dims, l, 5, integrator, riemann, recon=recon, emf=emf)
     o, ao = O.copy_state(s), copy_pot(a)
     p = O.Params(n, n, n, integrator={"rk2": O.RK2, "rk3": O.RK3}[integrator],
                  riemann={"hlld": O.HLLD, "hll": O.HLL}[riemann],
-                 recon={"plm": O.PLM, "ppm": O.PPM}[recon])
+                 recon={"plm": O.PLM, "limo3": O.LIMO3, "ppm": O.PPM}[recon],
+                 emf={"ec": O.EMF_EC, "uct_hll": O.EMF_UCT_HLL}[emf])
     t, dt = 0.0, 0.0
     od = []
     for _ in range(5):

@@ -18,11 +18,12 @@ def copy_pot(a):
     return {"ax": a["ax"].copy(), "ay": a["ay"].copy(), "az": a["az"].copy(), "b0": a["b0"]}
 
 
-@pytest.mark.parametrize("integ", [O.RK2, O.RK3])
-def test_equivalent_to_face_update(integ):
+@pytest.mark.parametrize("integ,emf", [(O.RK2, O.EMF_EC), (O.RK3, O.EMF_EC),
+                                       (O.RK2, O.EMF_UCT_HLL)])
+def test_equivalent_to_face_update(integ, emf):
     n = 16
     s, a = I.orszag_tang_3d(n, potential=True)
-    p = O.Params(n, n, n, integrator=integ)
+    p = O.Params(n, n, n, integrator=integ, emf=emf)
     sa, aa = O.copy_state(s), copy_pot(a)
     O.step_vp(p, sa, aa, 0.0, 0.0, 12)
     sb = O.copy_state(sa)
