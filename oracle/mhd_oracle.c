@@ -84,10 +84,8 @@ static int check_params(const orc_params* p) {
     return ORC_ERR_INVALID_ARG;
   if (p->recon != ORC_PLM && p->recon != ORC_LIMO3 && p->recon != ORC_PPM)
     return ORC_ERR_INVALID_ARG;
-  /* the edge solve reconstructs face data with the three-cell limiters and needs
-   * a magnetic Riemann solver */
-  if (p->emf == ORC_EMF_UCT_HLL && (p->recon == ORC_PPM || p->riemann == ORC_HLLC))
-    return ORC_ERR_INVALID_ARG;
+  /* the edge solve needs a magnetic Riemann solver */
+  if (p->emf == ORC_EMF_UCT_HLL && p->riemann == ORC_HLLC) return ORC_ERR_INVALID_ARG;
   return ORC_OK;
 }
 
@@ -724,10 +722,18 @@ static double uct_part(double ap, double am, double vl, double bl, double vr, do
 static double dmax(double a, double b) { return a > b ? a : b; }
 
 /* the value at the edge from the low side (upper face of the cell below) and
- * from the high side, from four face values around it along the line */
+ * from the high side (lower face of the cell above), with the cell
+ * reconstruction, from six face values q[0..5] around it along the line (the
+ * edge lies between q[2] and q[3]; the three-cell limiters read q[1..4]) */
 static void to_edge(int recon, const double* q, double* lo_side, double* hi_side) {
-  *lo_side = recon_hi(recon, q[0], q[1], q[2]);
-  *hi_side = recon_lo(recon, q[1], q[2], q[3]);
+  if (recon == ORC_PPM) {
+    double unused;
+    ppm_faces(q, &unused, lo_side);
+    ppm_faces(q + 1, hi_side, &unused);
+    return;
+  }
+  *lo_side = recon_hi(recon, q[1], q[2], q[3]);
+  *hi_side = recon_lo(recon, q[2], q[3], q[4]);
 }
 
 static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
@@ -743,11 +749,11 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
       for (int i = 0; i < g->nx; ++i) {
         int im = dn(i, g->nx);
         long c = at(g, i, j, k);
-        double b[4], v[4], bl, br, vl, vr;
+        double b[6], v[6], bl, br, vl, vr;
         /* E_z at (i-1/2, j-1/2, k): P = x, Q = y */
         {
-          for (int q = 0; q < 4; ++q) {  /* y-faces (i-2 .. i+1, j-1/2) */
-            long f = at(g, wrap(i - 2 + q, g->nx), j, k);
+          for (int q = 0; q < 6; ++q) {  /* y-faces (i-3 .. i+2, j-1/2) */
+            long f = at(g, wrap(i - 3 + q, g->nx), j, k);
             b[q] = s->by[f];
             v[q] = fy[F_VT2][f];  /* v_x on a y-face */
           }
@@ -756,8 +762,8 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           long cjm = at(g, i, jm, k);
           double fp = uct_part(dmax(fx[F_AP][cjm], fx[F_AP][c]), dmax(fx[F_AM][cjm], fx[F_AM][c]),
                                vl, bl, vr, br);
-          for (int q = 0; q < 4; ++q) {  /* x-faces (i-1/2, j-2 .. j+1) */
-            long f = at(g, i, wrap(j - 2 + q, g->ny), k);
+          for (int q = 0; q < 6; ++q) {  /* x-faces (i-1/2, j-3 .. j+2) */
+            long f = at(g, i, wrap(j - 3 + q, g->ny), k);
             b[q] = s->bx[f];
             v[q] = fx[F_VT1][f];  /* v_y on an x-face */
           }
@@ -770,8 +776,8 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
         }
         /* E_x at (i, j-1/2, k-1/2): P = y, Q = z */
         {
-          for (int q = 0; q < 4; ++q) {  /* z-faces (i, j-2 .. j+1, k-1/2) */
-            long f = at(g, i, wrap(j - 2 + q, g->ny), k);
+          for (int q = 0; q < 6; ++q) {  /* z-faces (i, j-3 .. j+2, k-1/2) */
+            long f = at(g, i, wrap(j - 3 + q, g->ny), k);
             b[q] = s->bz[f];
             v[q] = fz[F_VT2][f];  /* v_y on a z-face */
           }
@@ -780,8 +786,8 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           long ckm = at(g, i, j, km);
           double fp = uct_part(dmax(fy[F_AP][ckm], fy[F_AP][c]), dmax(fy[F_AM][ckm], fy[F_AM][c]),
                                vl, bl, vr, br);
-          for (int q = 0; q < 4; ++q) {  /* y-faces (i, j-1/2, k-2 .. k+1) */
-            long f = at(g, i, j, wrap(k - 2 + q, g->nz));
+          for (int q = 0; q < 6; ++q) {  /* y-faces (i, j-1/2, k-3 .. k+2) */
+            long f = at(g, i, j, wrap(k - 3 + q, g->nz));
             b[q] = s->by[f];
             v[q] = fy[F_VT1][f];  /* v_z on a y-face */
           }
@@ -794,8 +800,8 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
         }
         /* E_y at (i-1/2, j, k-1/2): P = z, Q = x */
         {
-          for (int q = 0; q < 4; ++q) {  /* x-faces (i-1/2, j, k-2 .. k+1) */
-            long f = at(g, i, j, wrap(k - 2 + q, g->nz));
+          for (int q = 0; q < 6; ++q) {  /* x-faces (i-1/2, j, k-3 .. k+2) */
+            long f = at(g, i, j, wrap(k - 3 + q, g->nz));
             b[q] = s->bx[f];
             v[q] = fx[F_VT2][f];  /* v_z on an x-face */
           }
@@ -804,8 +810,8 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           long cim = at(g, im, j, k);
           double fp = uct_part(dmax(fz[F_AP][cim], fz[F_AP][c]), dmax(fz[F_AM][cim], fz[F_AM][c]),
                                vl, bl, vr, br);
-          for (int q = 0; q < 4; ++q) {  /* z-faces (i-2 .. i+1, j, k-1/2) */
-            long f = at(g, wrap(i - 2 + q, g->nx), j, k);
+          for (int q = 0; q < 6; ++q) {  /* z-faces (i-3 .. i+2, j, k-1/2) */
+            long f = at(g, wrap(i - 3 + q, g->nx), j, k);
             b[q] = s->bz[f];
             v[q] = fz[F_VT1][f];  /* v_x on a z-face */
           }

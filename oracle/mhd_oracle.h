@@ -23,7 +23,7 @@ enum { ORC_HLLD = 0, ORC_HLL = 1, ORC_HLLC = 2 }; /* HLLC: hydrodynamics, B = 0 
 enum { ORC_RK2 = 0, ORC_EULER = 1, ORC_RK3 = 2 };
 /* corner-EMF schemes of Sec. 2.4: E^c (default), E^0, arithmetic average (all
  * from the face fluxes), and UCT-HLL, a 2D HLL Riemann solve at each edge
- * (MHD solvers with PLM or LimO3 only) */
+ * (MHD solvers only) */
 enum { ORC_EMF_EC = 0, ORC_EMF_E0 = 1, ORC_EMF_ARITH = 2, ORC_EMF_UCT_HLL = 3 };
 /* reconstructions of Sec. 2.3: van Leer PLM (default), LimO3, PPM */
 enum { ORC_PLM = 0, ORC_LIMO3 = 1, ORC_PPM = 2 };
