@@ -61,17 +61,16 @@ typedef enum { MHD_HLLD = 0, MHD_HLL = 1, MHD_HLLC = 2 } mhd_riemann;
  * UCT-HLL, a 2D HLL Riemann solve at each edge (Londrillo & Del Zanna 2004, in
  * the form of Mignone & Del Zanna 2021), which splits each edge EMF into two 1D
  * HLL fluxes across the edge from the faces' normal fields and HLL-averaged
- * transverse velocities reconstructed to it (with the cell reconstruction's
- * limiter).  UCT-HLL is built for HLLD/HLL with MHD_PLM or MHD_LIMO3 and either
- * CT form (else MHD_ERR_UNSUPPORTED); it runs two extra
+ * transverse velocities reconstructed to it (with the cell reconstruction).
+ * UCT-HLL is built for HLLD/HLL with every reconstruction and either CT form
+ * (else MHD_ERR_UNSUPPORTED); it runs two extra
  * one-thread-per-cell launches per stage and needs 15 more arrays of one field
  * in the workspace (mhd_workspace_bytes accounts for them). */
 typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2, MHD_EMF_UCT_HLL = 3 } mhd_emf;
 /* Reconstructions of Sec. 2.3, all on the primitives: van Leer PLM (default),
  * the compact third-order LimO3 limiter (Cada & Torrilhon 2009), and PPM
  * (Colella & Woodward 1984) with the extremum-preserving limiter of Colella &
- * Sekora (2008).  PPM reads three cells each way; it combines with every EMF
- * scheme but UCT-HLL and with both CT forms. */
+ * Sekora (2008).  PPM reads three cells each way. */
 typedef enum { MHD_PLM = 0, MHD_LIMO3 = 1, MHD_PPM = 2 } mhd_recon;
 /* Constrained transport (Sec. 2.4): the face field updated by the discrete
  * Stokes theorem, or carried by an edge vector potential A (eqs. ind_vec:

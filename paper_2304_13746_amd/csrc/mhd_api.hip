@@ -504,10 +504,9 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH &&
       p->emf != MHD_EMF_UCT_HLL)
     return MHD_ERR_UNSUPPORTED;
-  // UCT-HLL is built for the MHD solvers with PLM or LimO3 (with the potential
-  // form under its FP64 rule below)
-  if (p->emf == MHD_EMF_UCT_HLL && (p->riemann == MHD_HLLC || p->recon == MHD_PPM))
-    return MHD_ERR_UNSUPPORTED;
+  // UCT-HLL is built for the MHD solvers (with the potential form under its
+  // FP64 rule below)
+  if (p->emf == MHD_EMF_UCT_HLL && p->riemann == MHD_HLLC) return MHD_ERR_UNSUPPORTED;
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3 && p->recon != MHD_PPM)
     return MHD_ERR_UNSUPPORTED;
   if (p->ct != MHD_CT_FACE && p->ct != MHD_CT_VECPOT) return MHD_ERR_INVALID_ARG;

@@ -1039,13 +1039,10 @@ static hipError_t launch_mode(const BatchArgs& ba, hipStream_t st, bool prepare)
 template <typename R, int SOLVER, int RECON, int TX, int TY>
 static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) {
   if (ba.emf == EMF_UCT) {
-    // UCT-HLL is built with PLM or LimO3; its stage kernel leaves the field to
-    // the edge-solve launches, so one build serves both CT forms (the
-    // potential form in FP64)
-    if constexpr (RECON == RECON_PLM || RECON == RECON_LIMO3) {
-      if (ba.ct == CT_FACE || (ba.ct == CT_VECPOT && sizeof(R) == 8))
-        return launch_mode<R, SOLVER, RECON, EMF_UCT, CT_FACE, TX, TY>(ba, st, prepare);
-    }
+    // UCT-HLL: the stage kernel leaves the field to the edge-solve launches,
+    // so one build serves both CT forms (the potential form in FP64)
+    if (ba.ct == CT_FACE || (ba.ct == CT_VECPOT && sizeof(R) == 8))
+      return launch_mode<R, SOLVER, RECON, EMF_UCT, CT_FACE, TX, TY>(ba, st, prepare);
     return hipErrorInvalidValue;
   }
   if (ba.ct == CT_VECPOT) {

@@ -12,7 +12,7 @@
 //              F_Q the 1D HLL flux of v_Q B_P across the edge along Q, from
 //              the two P-faces that meet there (their normal field B_P and
 //              averaged v_Q, reconstructed along Q to the edge from either
-//              side with the cell limiter, van Leer or LimO3), with the larger
+//              side with the cell reconstruction: PLM, LimO3 or PPM), with the larger
 //              speeds of the two Q-faces that
 //              share the edge; F_P likewise along P from the two Q-faces:
 //                F = (a+ vL bL + a- vR bR - a+ a- (bR - bL)) / (a+ + a-);
@@ -56,18 +56,41 @@ __device__ __forceinline__ R uct_part(R ap, R am, R vl, R bl, R vr, R br) {
 
 // the 1D HLL flux across one edge from four face values of b and v along the
 // line through it (indices o[0..3]) and the speeds of the faces it crosses
+// face values along the line through an edge: four (the three-cell limiters)
+// or six (PPM), the edge between the middle two
+template <int RECON>
+constexpr int kLine = RECON == RECON_PPM ? 6 : 4;
+
+// the values at the edge from its low and high sides, with the cell
+// reconstruction
+template <int RECON, typename R>
+__device__ __forceinline__ void to_edge(const R* q, R& lo_side, R& hi_side) {
+  if constexpr (RECON == RECON_PPM) {
+    R lo, hi;
+    ppm_limit(q[0], q[1], q[2], q[3], q[4], ppm_interface(q[0], q[1], q[2], q[3]),
+              ppm_interface(q[1], q[2], q[3], q[4]), lo, hi);
+    lo_side = hi;
+    ppm_limit(q[1], q[2], q[3], q[4], q[5], ppm_interface(q[1], q[2], q[3], q[4]),
+              ppm_interface(q[2], q[3], q[4], q[5]), lo, hi);
+    hi_side = lo;
+  } else {
+    lo_side = recon_hi<RECON>(q[0], q[1], q[2]);
+    hi_side = recon_lo<RECON>(q[1], q[2], q[3]);
+  }
+}
+
 template <int RECON, typename R>
 __device__ __forceinline__ R edge_flux(const R* b, const R* v, const long long* o, R ap, R am) {
-  R bq[4], vq[4];
+  constexpr int NQ = kLine<RECON>;
+  R bq[NQ], vq[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     bq[q] = ld(b, o[q]);
     vq[q] = ld(v, o[q]);
   }
-  const R bl = recon_hi<RECON>(bq[0], bq[1], bq[2]);
-  const R br = recon_lo<RECON>(bq[1], bq[2], bq[3]);
-  const R vl = recon_hi<RECON>(vq[0], vq[1], vq[2]);
-  const R vr = recon_lo<RECON>(vq[1], vq[2], vq[3]);
+  R bl, br, vl, vr;
+  to_edge<RECON>(bq, bl, br);
+  to_edge<RECON>(vq, vl, vr);
   return uct_part(ap, am, vl, bl, vr, br);
 }
 
@@ -93,14 +116,15 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   R* u = static_cast<R*>(d->uct);
   const long long us = d->ustride;
   auto fa = [&](int dir, int q) -> const R* { return u + (long long)(4 * dir + q) * us; };
-  long long o[4];
+  constexpr int NQ = kLine<RECON>, Q0 = NQ / 2;  // line offsets -Q0 .. NQ-Q0-1
+  long long o[NQ];
   // E_z at (i-1/2, j-1/2, k): P = x, Q = y
   {
     const long long cjm = yj(-1), cim = xi(-1);
-    for (int q = 0; q < 4; ++q) o[q] = xi(q - 2);  // y-faces (i-2 .. i+1, j-1/2)
+    for (int q = 0; q < NQ; ++q) o[q] = xi(q - Q0);  // y-faces along x around i-1/2
     const R fp = edge_flux<RECON>(by, fa(1, U_VT2), o, rmax(ld(fa(0, U_AP), cjm), ld(fa(0, U_AP), c)),
                            rmax(ld(fa(0, U_AM), cjm), ld(fa(0, U_AM), c)));
-    for (int q = 0; q < 4; ++q) o[q] = yj(q - 2);  // x-faces (i-1/2, j-2 .. j+1)
+    for (int q = 0; q < NQ; ++q) o[q] = yj(q - Q0);  // x-faces along y around j-1/2
     const R fq = edge_flux<RECON>(bx, fa(0, U_VT1), o, rmax(ld(fa(1, U_AP), cim), ld(fa(1, U_AP), c)),
                            rmax(ld(fa(1, U_AM), cim), ld(fa(1, U_AM), c)));
     u[(U_E + 2) * us + c] = fq - fp;
@@ -108,10 +132,10 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   // E_x at (i, j-1/2, k-1/2): P = y, Q = z
   {
     const long long ckm = zk(-1), cjm = yj(-1);
-    for (int q = 0; q < 4; ++q) o[q] = yj(q - 2);  // z-faces (i, j-2 .. j+1, k-1/2)
+    for (int q = 0; q < NQ; ++q) o[q] = yj(q - Q0);  // z-faces along y around j-1/2
     const R fp = edge_flux<RECON>(bz, fa(2, U_VT2), o, rmax(ld(fa(1, U_AP), ckm), ld(fa(1, U_AP), c)),
                            rmax(ld(fa(1, U_AM), ckm), ld(fa(1, U_AM), c)));
-    for (int q = 0; q < 4; ++q) o[q] = zk(q - 2);  // y-faces (i, j-1/2, k-2 .. k+1)
+    for (int q = 0; q < NQ; ++q) o[q] = zk(q - Q0);  // y-faces along z around k-1/2
     const R fq = edge_flux<RECON>(by, fa(1, U_VT1), o, rmax(ld(fa(2, U_AP), cjm), ld(fa(2, U_AP), c)),
                            rmax(ld(fa(2, U_AM), cjm), ld(fa(2, U_AM), c)));
     u[U_E * us + c] = fq - fp;
@@ -119,10 +143,10 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   // E_y at (i-1/2, j, k-1/2): P = z, Q = x
   {
     const long long cim = xi(-1), ckm = zk(-1);
-    for (int q = 0; q < 4; ++q) o[q] = zk(q - 2);  // x-faces (i-1/2, j, k-2 .. k+1)
+    for (int q = 0; q < NQ; ++q) o[q] = zk(q - Q0);  // x-faces along z around k-1/2
     const R fp = edge_flux<RECON>(bx, fa(0, U_VT2), o, rmax(ld(fa(2, U_AP), cim), ld(fa(2, U_AP), c)),
                            rmax(ld(fa(2, U_AM), cim), ld(fa(2, U_AM), c)));
-    for (int q = 0; q < 4; ++q) o[q] = xi(q - 2);  // z-faces (i-2 .. i+1, j, k-1/2)
+    for (int q = 0; q < NQ; ++q) o[q] = xi(q - Q0);  // z-faces along x around i-1/2
     const R fq = edge_flux<RECON>(bz, fa(2, U_VT1), o, rmax(ld(fa(0, U_AP), ckm), ld(fa(0, U_AP), c)),
                            rmax(ld(fa(0, U_AM), ckm), ld(fa(0, U_AM), c)));
     u[(U_E + 1) * us + c] = fq - fp;
@@ -176,11 +200,14 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_ct(BatchArgs ba) {
 template <typename R>
 hipError_t uct_launch(const BatchArgs& ba, int recon, bool update_b, hipStream_t st) {
   if (ba.nbox < 1 || ba.nbox > kMaxBatch || ba.total < 1) return hipErrorInvalidValue;
-  if (recon != RECON_PLM && recon != RECON_LIMO3) return hipErrorInvalidValue;
-  if (recon == RECON_LIMO3)
+  if (recon == RECON_PPM)
+    hipLaunchKernelGGL((k_uct_emf<R, RECON_PPM>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
+  else if (recon == RECON_LIMO3)
     hipLaunchKernelGGL((k_uct_emf<R, RECON_LIMO3>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
-  else
+  else if (recon == RECON_PLM)
     hipLaunchKernelGGL((k_uct_emf<R, RECON_PLM>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
+  else
+    return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !update_b) return e;
   hipLaunchKernelGGL(k_uct_ct<R>, dim3(ba.total), dim3(kUctBlock), 0, st, ba);

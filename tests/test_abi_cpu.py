@@ -56,17 +56,17 @@ def test_workspace_bytes_and_argument_checks():
     q = make_params(8, 8, 8)
     q.emf = 7
     assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED
-    # PPM: every EMF scheme but UCT-HLL, both CT forms (the potential form in FP64)
-    for kw in ({"recon": "ppm", "emf": "uct_hll"}, {"recon": "ppm", "riemann": "hllc", "ct": "vecpot"},
+    # PPM: every EMF scheme, both CT forms (the potential form in FP64)
+    for kw in ({"recon": "ppm", "riemann": "hllc", "ct": "vecpot"},
                {"recon": "ppm", "ct": "vecpot", "precision": "fp32"}):
         q = make_params(8, 8, 8, **kw)
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED, kw
     for kw in ({"recon": "ppm", "emf": "e0"}, {"recon": "ppm", "emf": "arith"},
-               {"recon": "ppm", "ct": "vecpot"}):
+               {"recon": "ppm", "ct": "vecpot"}, {"recon": "ppm", "emf": "uct_hll"}):
         q = make_params(8, 8, 8, **kw)
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE, kw
     # UCT-HLL: MHD solvers, PLM or LimO3, face-field CT
-    for kw in ({"emf": "uct_hll", "riemann": "hllc"}, {"emf": "uct_hll", "recon": "ppm"},
+    for kw in ({"emf": "uct_hll", "riemann": "hllc"},
                {"emf": "uct_hll", "ct": "vecpot", "precision": "fp32"}):
         q = make_params(8, 8, 8, **kw)
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED, kw

@@ -151,10 +151,15 @@ def test_ppm_other_emf_schemes_fp64_bit_exact(emf):
     assert gd == od
 
 
-def test_ppm_with_uct_rejected():
-    """The UCT-HLL edge solve reconstructs with three-point limiters only: PPM
-    with it is refused at creation, not run."""
+def test_ppm_with_uct_fp64_bit_exact():
+    """PPM with the UCT-HLL edge solve (its face data reconstructed to the
+    edges with PPM too), RK3: bit-identical to the oracle."""
     need_gpu()
-    from paper_2304_13746_amd.box import MHDBox
-    with pytest.raises(RuntimeError):
-        MHDBox(16, 16, 16, recon="ppm", emf="uct_hll")
+    dims = (37, 29, 11)
+    s = I.turbulence(dims, seed=61, kpeak=2.0, mach=0.9, b0=(0.2, 0.15, -0.25))
+    l = s.pop("_l")
+    print("ppm uct", flush=True)
+    g, o, gd, od, _ = run_both(s, dims, 3, l=l, per_step=True, recon="ppm", emf="uct_hll",
+                               integrator="rk3")
+    assert bit_equal(g, o)
+    assert gd == od
