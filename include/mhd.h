@@ -75,7 +75,7 @@ typedef enum { MHD_PLM = 0, MHD_LIMO3 = 1, MHD_PPM = 2 } mhd_recon;
 /* Constrained transport (Sec. 2.4): the face field updated by the discrete
  * Stokes theorem, or carried by an edge vector potential A (eqs. ind_vec:
  * dA/dt = -E, B = b0 + curl A, b0 the uniform mean field); the potential form
- * is built for FP64 with the E^c or UCT-HLL scheme and HLLD/HLL. */
+ * is built for FP64 with HLLD/HLL and every EMF scheme. */
 typedef enum { MHD_CT_FACE = 0, MHD_CT_VECPOT = 1 } mhd_ct;
 typedef enum { MHD_RK2 = 0, MHD_EULER = 1, MHD_RK3 = 2 } mhd_integrator; /* Tab. weights */
 

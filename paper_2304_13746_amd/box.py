@@ -101,7 +101,10 @@ class MHDBox:
                 continue  # derived from the potential
             a = state[f]
             if isinstance(a, np.ndarray):
-                a = torch.from_numpy(np.ascontiguousarray(a))
+                a = np.ascontiguousarray(a)
+                if not a.flags.writeable:  # torch wraps only writable arrays
+                    a = a.copy()
+                a = torch.from_numpy(a)
             a = a.to(device=self.device, dtype=self.dtype).contiguous()
             if tuple(a.shape) != self.shape:
                 raise ValueError(f"field {f}: shape {tuple(a.shape)} != {self.shape}")

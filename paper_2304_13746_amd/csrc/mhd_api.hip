@@ -510,9 +510,7 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3 && p->recon != MHD_PPM)
     return MHD_ERR_UNSUPPORTED;
   if (p->ct != MHD_CT_FACE && p->ct != MHD_CT_VECPOT) return MHD_ERR_INVALID_ARG;
-  if (p->ct == MHD_CT_VECPOT &&
-      (p->precision != MHD_FP64 || (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_UCT_HLL) ||
-       p->riemann == MHD_HLLC))
+  if (p->ct == MHD_CT_VECPOT && (p->precision != MHD_FP64 || p->riemann == MHD_HLLC))
     return MHD_ERR_UNSUPPORTED;
   if (p->integrator != MHD_RK2 && p->integrator != MHD_EULER && p->integrator != MHD_RK3)
     return MHD_ERR_INVALID_ARG;

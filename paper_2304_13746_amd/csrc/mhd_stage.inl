@@ -1045,9 +1045,12 @@ static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) 
       return launch_mode<R, SOLVER, RECON, EMF_UCT, CT_FACE, TX, TY>(ba, st, prepare);
     return hipErrorInvalidValue;
   }
-  if (ba.ct == CT_VECPOT) {
+  if (ba.ct == CT_VECPOT) {  // the potential form is built for FP64
     if constexpr (sizeof(R) == 8) {
       if (ba.emf == EMF_EC) return launch_mode<R, SOLVER, RECON, EMF_EC, CT_VECPOT, TX, TY>(ba, st, prepare);
+      if (ba.emf == EMF_E0) return launch_mode<R, SOLVER, RECON, EMF_E0, CT_VECPOT, TX, TY>(ba, st, prepare);
+      if (ba.emf == EMF_ARITH)
+        return launch_mode<R, SOLVER, RECON, EMF_ARITH, CT_VECPOT, TX, TY>(ba, st, prepare);
     }
     return hipErrorInvalidValue;
   }

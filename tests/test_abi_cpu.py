@@ -72,7 +72,8 @@ def test_workspace_bytes_and_argument_checks():
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED, kw
     for kw in ({"recon": "ppm"}, {"recon": "ppm", "riemann": "hllc", "emf": "e0"},
                {"emf": "uct_hll"}, {"emf": "uct_hll", "riemann": "hll", "precision": "fp32"},
-               {"emf": "uct_hll", "recon": "limo3"}, {"emf": "uct_hll", "ct": "vecpot"}):
+               {"emf": "uct_hll", "recon": "limo3"}, {"emf": "uct_hll", "ct": "vecpot"},
+               {"emf": "e0", "ct": "vecpot"}, {"emf": "arith", "ct": "vecpot", "riemann": "hll"}):
         q = make_params(8, 8, 8, **kw)  # accepted up to the (missing) workspace
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE, kw
     # UCT-HLL takes 15 more arrays of one field in the workspace

@@ -35,7 +35,8 @@ def gpu_run(s, a, dims, l, nsteps, integrator="rk2", riemann="hlld", stream=None
 
 @pytest.mark.parametrize("integrator,recon,emf", [("rk2", "plm", "ec"), ("rk3", "plm", "ec"),
                                                   ("rk3", "ppm", "ec"), ("rk2", "plm", "uct_hll"),
-                                                  ("rk3", "limo3", "uct_hll")])
+                                                  ("rk3", "limo3", "uct_hll"), ("rk2", "plm", "e0"),
+                                                  ("rk3", "ppm", "arith")])
 @pytest.mark.parametrize("riemann", ["hlld", "hll"])
 def test_vecpot_fp64_bit_exact(integrator, riemann, recon, emf):
     need_gpu()
@@ -48,7 +49,8 @@ def test_vecpot_fp64_bit_exact(integrator, riemann, recon, emf):
     p = O.Params(n, n, n, integrator={"rk2": O.RK2, "rk3": O.RK3}[integrator],
                  riemann={"hlld": O.HLLD, "hll": O.HLL}[riemann],
                  recon={"plm": O.PLM, "limo3": O.LIMO3, "ppm": O.PPM}[recon],
-                 emf={"ec": O.EMF_EC, "uct_hll": O.EMF_UCT_HLL}[emf])
+                 emf={"ec": O.EMF_EC, "e0": O.EMF_E0, "arith": O.EMF_ARITH,
+                      "uct_hll": O.EMF_UCT_HLL}[emf])
     t, dt = 0.0, 0.0
     od = []
     for _ in range(5):
