@@ -16,7 +16,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmhd.so")
 # a plain host program that drives the library through the C ABI only
 EXAMPLE = os.path.join(HERE, "mhd_abi_example")
-SOURCES = ["mhd_api.hip", "mhd_stage_f64.hip", "mhd_stage_f32.hip", "mhd_vpot.hip", "mhd_uct.hip"]
+# the stage kernels in one unit per precision and Riemann solver, compiled in parallel
+STAGE = [f"mhd_stage_{p}_{s}.hip" for p in ("f64", "f32") for s in ("hlld", "hll", "hllc")]
+SOURCES = ["mhd_api.hip", *STAGE, "mhd_vpot.hip", "mhd_uct.hip"]
 ARCH = os.environ.get("MHD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
@@ -24,7 +26,7 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
          "-Wno-unused-variable", "-Wno-unused-function"]
 # FP64 (and the host-side API) round exactly as written, like the CPU reference;
 # the FP32 kernels, checked against a tolerance, may fuse multiply-adds.
-CONTRACT = {"mhd_stage_f32.hip": "-ffp-contract=fast"}
+CONTRACT = {s: "-ffp-contract=fast" for s in STAGE if "_f32_" in s}
 
 
 def _compile(src: str, defines=(), tag: str = "") -> str:
@@ -42,7 +44,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     into ``out``."""
     os.makedirs(BUILD, exist_ok=True)
     tag = "" if out == LIB else "_" + os.path.basename(out).replace(".so", "")
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(s, defines, tag), SOURCES))
     tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]

@@ -211,6 +211,20 @@ __global__ void k_diag_final(const double* part, int nblocks, double dv, double 
 
 int hip_fail(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_HIP; }
 
+// The stage kernels of the context's precision and Riemann solver.
+hipError_t stage_kernel(const mhd_params* p, const BatchArgs& ba, int tile, hipStream_t st,
+                        bool prepare) {
+  const int rc = p->recon;
+  if (p->precision == MHD_FP32) {
+    if (p->riemann == MHD_HLL) return stage_f32_hll(ba, tile, rc, st, prepare);
+    if (p->riemann == MHD_HLLC) return stage_f32_hllc(ba, tile, rc, st, prepare);
+    return stage_f32_hlld(ba, tile, rc, st, prepare);
+  }
+  if (p->riemann == MHD_HLL) return stage_f64_hll(ba, tile, rc, st, prepare);
+  if (p->riemann == MHD_HLLC) return stage_f64_hllc(ba, tile, rc, st, prepare);
+  return stage_f64_hlld(ba, tile, rc, st, prepare);
+}
+
 void fields_of(const mhd_state_view* v, void* out[11]) {
   out[0] = v->rho; out[1] = v->mx; out[2] = v->my; out[3] = v->mz;
   out[4] = v->en; out[5] = v->bx; out[6] = v->by; out[7] = v->bz;
@@ -249,10 +263,7 @@ hipError_t launch_stage(mhd_ctx* const* c, const Roles* r, int n, int mode, doub
     ba.start[m] = g;
     ba.total = g;
     const mhd_ctx* c0 = c[i0];
-    const int rc = c0->p.recon;
-    hipError_t e = c0->p.precision == MHD_FP32
-                       ? stage_f32(ba, c0->tile, c0->p.riemann, rc, st, false)
-                       : stage_f64(ba, c0->tile, c0->p.riemann, rc, st, false);
+    hipError_t e = stage_kernel(&c0->p, ba, c0->tile, st, false);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -419,8 +430,7 @@ int apply_shape(mhd_ctx* c, int tile, int zchunk) {
   BatchArgs none = {};
   none.emf = p->emf;
   none.ct = p->ct;
-  hipError_t e = p->precision == MHD_FP32 ? stage_f32(none, tile, p->riemann, p->recon, nullptr, true)
-                                          : stage_f64(none, tile, p->riemann, p->recon, nullptr, true);
+  hipError_t e = stage_kernel(p, none, tile, nullptr, true);
   if (e != hipSuccess) return MHD_ERR_HIP;
   const int lz = zchunk > 0 ? (zchunk < p->nz ? zchunk : p->nz) : choose_lz(tile, p->nx, p->ny, p->nz);
   BoxDesc d = {};

@@ -90,9 +90,14 @@ struct BatchArgs {
   unsigned char src[kMaxBatch], dst[kMaxBatch], base[kMaxBatch];
 };
 
-// stage launch for one precision (mhd_stage_f64.hip / mhd_stage_f32.hip)
-hipError_t stage_f64(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
-                     bool prepare);
+// stage launch for one precision and Riemann solver (mhd_stage_<f64|f32>_<solver>.hip);
+// with prepare, raise the LDS limit of the kernels b.emf and b.ct name instead
+hipError_t stage_f64_hlld(const BatchArgs& b, int tile, int recon, hipStream_t st, bool prepare);
+hipError_t stage_f64_hll(const BatchArgs& b, int tile, int recon, hipStream_t st, bool prepare);
+hipError_t stage_f64_hllc(const BatchArgs& b, int tile, int recon, hipStream_t st, bool prepare);
+hipError_t stage_f32_hlld(const BatchArgs& b, int tile, int recon, hipStream_t st, bool prepare);
+hipError_t stage_f32_hll(const BatchArgs& b, int tile, int recon, hipStream_t st, bool prepare);
+hipError_t stage_f32_hllc(const BatchArgs& b, int tile, int recon, hipStream_t st, bool prepare);
 // vector-potential form (FP64): A_dst = w (A_src - dt E) + w0 A_base on every
 // edge, with E left in the output's face-field slots by the stage kernel (with
 // UCT-HLL, ba.emf == 3, in the edge-EMF scratch arrays), then B_dst = b0 + curl
@@ -108,8 +113,6 @@ constexpr int kUctArrays = 15;
 // (with update_b = false only the edge EMFs: the potential form takes them)
 hipError_t uct_f64(const BatchArgs& b, int recon, bool update_b, hipStream_t st);
 hipError_t uct_f32(const BatchArgs& b, int recon, bool update_b, hipStream_t st);
-hipError_t stage_f32(const BatchArgs& b, int tile, int solver, int recon, hipStream_t st,
-                     bool prepare);
 int tile_dims(int tile, int* tx, int* ty);
 
 }  // namespace mhd

@@ -1035,7 +1035,7 @@ static hipError_t launch_mode(const BatchArgs& ba, hipStream_t st, bool prepare)
   return launch_one<R, SOLVER, RECON, EMF, CT, MODE_MEASURE, TX, TY>(ba, st, prepare);
 }
 
-// The vector-potential form is built for FP64 with the default EMF scheme.
+// The vector-potential form is built for FP64, with every EMF scheme.
 template <typename R, int SOLVER, int RECON, int TX, int TY>
 static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) {
   if (ba.emf == EMF_UCT) {
@@ -1083,23 +1083,15 @@ static hipError_t launch_recon(const BatchArgs& ba, int recon, hipStream_t st, b
   }
 }
 
-template <typename R, int TX, int TY>
-static hipError_t launch_tile(const BatchArgs& ba, int solver, int recon, hipStream_t st,
-                              bool prepare) {
-  if (solver == SOLVER_HLLD) return launch_recon<R, SOLVER_HLLD, TX, TY>(ba, recon, st, prepare);
-  if (solver == SOLVER_HLL) return launch_recon<R, SOLVER_HLL, TX, TY>(ba, recon, st, prepare);
-  return launch_recon<R, SOLVER_HLLC, TX, TY>(ba, recon, st, prepare);
-}
-
 // Raise the LDS limit of every mode of one (solver, reconstruction, EMF) choice.
-template <typename R, int TX, int TY>
-static hipError_t prepare_tile(int solver, int recon, int emf, int ct) {
+template <typename R, int SOLVER, int TX, int TY>
+static hipError_t prepare_tile(int recon, int emf, int ct) {
   BatchArgs ba = {};
   ba.emf = emf;
   ba.ct = ct;
   for (int mode = 0; mode < 3; ++mode) {
     ba.mode = mode;
-    hipError_t e = launch_tile<R, TX, TY>(ba, solver, recon, nullptr, true);
+    hipError_t e = launch_recon<R, SOLVER, TX, TY>(ba, recon, nullptr, true);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
