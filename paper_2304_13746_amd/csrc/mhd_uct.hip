@@ -54,8 +54,6 @@ __device__ __forceinline__ R uct_part(R ap, R am, R vl, R bl, R vr, R br) {
   return dvd((ap * (vl * bl) + am * (vr * br)) - (ap * am) * (br - bl), ap + am);
 }
 
-// the 1D HLL flux across one edge from four face values of b and v along the
-// line through it (indices o[0..3]) and the speeds of the faces it crosses
 // face values along the line through an edge: four (the three-cell limiters)
 // or six (PPM), the edge between the middle two
 template <int RECON>
@@ -79,6 +77,8 @@ __device__ __forceinline__ void to_edge(const R* q, R& lo_side, R& hi_side) {
   }
 }
 
+// the 1D HLL flux across one edge from the face values of b and v along the
+// line through it (indices o[0 .. kLine-1]) and the speeds of the faces it crosses
 template <int RECON, typename R>
 __device__ __forceinline__ R edge_flux(const R* b, const R* v, const long long* o, R ap, R am) {
   constexpr int NQ = kLine<RECON>;

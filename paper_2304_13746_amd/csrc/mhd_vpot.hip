@@ -13,6 +13,7 @@
 // is a separate launch because it reads the potential of neighbouring cells.
 #include <hip/hip_runtime.h>
 
+#include "mhd_device.h"
 #include "mhd_internal.h"
 
 namespace mhd {
@@ -36,7 +37,7 @@ __global__ void __launch_bounds__(kVpotBlock) k_vpot_update(BatchArgs ba) {
   const int si = ba.src[box], di = ba.dst[box], bi = ba.base[box];
   // the edge EMFs: in the output's face-field slots, or (UCT-HLL) in the
   // edge-EMF scratch arrays 12 .. 14
-  const bool uct = ba.emf == 3;
+  const bool uct = ba.emf == EMF_UCT;
   for (int f = 0; f < 3; ++f) {
     const double* as = static_cast<const double*>(d->buf[si][F_AX + f]);
     const double* e = uct ? static_cast<const double*>(d->uct) + (12 + f) * d->ustride
