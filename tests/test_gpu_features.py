@@ -43,6 +43,34 @@ def test_full_size_256_options_fp64_bit_exact(turb256, opts):
     assert gd == od and tg == to
 
 
+def test_full_size_256_vecpot_fp64_bit_exact(turb256):
+    """The vector-potential row the benchmark times: the same 256^3 input with its
+    uniform field carried as b0 and A = 0, one cycle in the default launch shape:
+    state, edge potential and next dt bit-identical to the oracle's potential
+    form."""
+    need_gpu()
+    from paper_2304_13746_amd.box import MHDBox
+    pot_f = ("ax", "ay", "az")
+    pot = I.uniform_field_potential(turb256["rho"].shape, (0.2, 0.0, 0.0))
+    print("256^3 vecpot", flush=True)
+    box = MHDBox(256, 256, 256, ct="vecpot", b0=pot["b0"])
+    st = dict(turb256)
+    st.update({k: pot[k] for k in pot_f})
+    box.set_state(st)
+    box.step(1)
+    g, tg, dg, rc = box.get_state_numpy()
+    box.close()
+    assert rc == 0
+    o = O.copy_state(turb256)
+    a = {"ax": pot["ax"].copy(), "ay": pot["ay"].copy(), "az": pot["az"].copy(), "b0": pot["b0"]}
+    t, dt, _ = O.step_vp(O.Params(256, 256, 256), o, a, 0.0, 0.0, 1)
+    for f in FIELDS:
+        assert np.array_equal(g[f], o[f]), f
+    for f in pot_f:
+        assert np.array_equal(g[f], a[f]), f
+    assert tg == t and dg == dt
+
+
 def test_full_size_256_fp32(turb256):
     """One FP32 cycle at 256^3 against the FP64 oracle on the rounded input:
     1e-5 norm-wise relative, face fields near E^c upwind ties to the looser

@@ -9,6 +9,10 @@ hold at any size.
   1e-5 in FP32 (the window property itself is pinned on the CPU in
   test_oracle_scheme.py).  20 cycles conserve mass, momentum, energy and the
   mean field to round-off and keep div B at round-off (compensated FP64 sums).
+* 512^3 Sedov-Taylor blast (B = 0) with HLLC and HLL: one RK2 cycle in the
+  default launch shape; the step equals the oracle's, windows over the blast,
+  across its rim, in the ambient gas and across the periodic corner equal the
+  oracle bit for bit, and the field stays exactly zero.
 * 64 uneven boxes (edges 16-128): one cycle of the autotuned, graph-captured
   batch against the oracle on every box.
 """
@@ -87,6 +91,35 @@ def test_c5_512_one_cycle_sampled(c5_state, precision):
             near = inner({"m": upwind_tie_cells(pw, w, t)})["m"]
             assert_fp32_close(got, ref, near)
     print(f"512^3 {precision}: worst window max rel {worst:.3e}")
+    box.close()
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "hll"])
+def test_sedov_512_one_cycle_sampled(riemann):
+    """The hydrodynamic rows the benchmark times (Sedov 512^3, FP64)."""
+    torch = need_gpu()
+    from paper_2304_13746_amd.box import MHDBox
+    rs = {"hllc": O.HLLC, "hll": O.HLL}[riemann]
+    s = I.sedov(N5)
+    dims = (N5, N5, N5)
+    print("sedov 512^3", riemann, flush=True)
+    box = MHDBox(*dims, riemann=riemann)
+    box.set_state(s)
+    box.step(1)
+    g, t, _, rc = box.get_state()
+    assert rc == 0
+    dt = 0.3 / O.max_invdt(O.Params(*dims, riemann=rs), s)
+    print(f"sedov 512^3 {riemann}: gpu dt {t!r} oracle dt {dt!r}", flush=True)
+    assert t == dt
+    c = N5 // 2
+    centers = [(c, c, c), (c + 3, c - 2, c + 1), (c + 12, c - 9, c + 5), (0, 0, 0)]
+    for ctr in centers:
+        idx = window_index(ctr, WIN, dims)
+        ref = oracle_window_cycle(s, idx, dims, (1.0, 1.0, 1.0), t, riemann=rs)
+        got = inner(gpu_window(torch, g, idx))
+        assert bit_equal(got, ref), ctr
+    for f in ("bx", "by", "bz"):
+        assert int(torch.count_nonzero(g[f])) == 0, f
     box.close()
 
 
