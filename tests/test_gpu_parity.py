@@ -10,6 +10,7 @@ import pytest
 
 import oracle as O
 from gpu_util import FIELDS, bit_equal, max_rel, need_gpu, run_both
+from paper_2304_13746_amd import _lib as L
 from paper_2304_13746_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -199,6 +200,43 @@ def test_sedov_hydro_fp64_bit_exact(riemann):
     assert gd == od and tg == to
     for f in ("bx", "by", "bz"):
         assert not g[f].any()
+
+
+@pytest.mark.parametrize("recon,integrator,tile", [("limo3", "rk3", L.TILE_24x8),
+                                                   ("plm", "rk3", L.TILE_18x11),
+                                                   ("limo3", "rk2", L.TILE_16x16),
+                                                   ("ppm", "rk2", L.TILE_24x8)])
+def test_hydro_hllc_options_fp64_bit_exact(recon, integrator, tile):
+    """The field-free HLLC build with each reconstruction, RK3 and every tile
+    on a ragged, non-cubic box of supersonic
+    hydrodynamic turbulence (B = 0): state and dt sequence bit-identical to the
+    oracle, the field exactly zero."""
+    need_gpu()
+    dims = (37, 29, 22)
+    s = I.turbulence(dims, seed=53, kpeak=2.0, mach=1.5, b0=(0.0, 0.0, 0.0))
+    l = s.pop("_l")
+    print("hydro hllc", recon, integrator, tile, dims, flush=True)
+    g, o, gd, od, (tg, to) = run_both(s, dims, 4, l=l, riemann="hllc", integrator=integrator,
+                                      per_step=True, recon=recon, tile=tile, zchunk=5)
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+    for f in ("bx", "by", "bz"):
+        assert not g[f].any()
+
+
+def test_hydro_hllc_limo3_fp32_within_tolerance():
+    """FP32 with HLLC and LimO3 + RK3 on the same kind of box: within 1e-5 of
+    the FP64 oracle (no field, so no E^c upwind ties)."""
+    need_gpu()
+    dims = (40, 24, 32)
+    s = I.turbulence(dims, seed=59, kpeak=2.0, mach=1.0, b0=(0.0, 0.0, 0.0))
+    l = s.pop("_l")
+    s = I.to_float32_exact(s)
+    g, o, _, _, _ = run_both(s, dims, 4, l=l, riemann="hllc", integrator="rk3",
+                             precision="fp32", recon="limo3")
+    err = max_rel(g, o)
+    print("hydro hllc limo3 fp32 max rel", err)
+    assert err <= 1e-5
 
 
 def test_sedov_hllc_fp32_within_tolerance():
