@@ -6,6 +6,7 @@ import pytest
 
 import oracle as O
 from gpu_util import FIELDS, bit_equal, need_gpu
+from paper_2304_13746_amd import _lib as L
 from paper_2304_13746_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -17,10 +18,10 @@ def copy_pot(a):
 
 
 def gpu_run(s, a, dims, l, nsteps, integrator="rk2", riemann="hlld", stream=None, recon="plm",
-            emf="ec"):
+            emf="ec", **kw):
     from paper_2304_13746_amd.box import MHDBox
     box = MHDBox(*dims, *l, integrator=integrator, riemann=riemann, ct="vecpot", b0=a["b0"],
-                 stream=stream, recon=recon, emf=emf)
+                 stream=stream, recon=recon, emf=emf, **kw)
     st = dict(s)
     st.update({k: a[k] for k in POT})
     box.set_state(st)
@@ -95,6 +96,37 @@ def test_vecpot_mean_field_ragged_batch():
     assert bit_equal(g, o)
     for f in POT:
         assert np.array_equal(g[f], ao[f])
+
+
+@pytest.mark.parametrize("dims,tile,emf", [((2, 9, 5), L.TILE_24x8, "ec"),
+                                           ((1, 1, 33), L.TILE_16x16, "uct_hll"),
+                                           ((33, 1, 1), L.TILE_18x11, "e0"),
+                                           ((37, 29, 11), L.TILE_18x11, "ec")])
+def test_vecpot_narrow_and_ragged_boxes(dims, tile, emf):
+    """Extents of one and two cells (the curl and the edge stencils wrap the
+    box) and a ragged box, with each tile and short z-chunks, from a seeded
+    non-uniform edge potential plus a mean field: state, potential and dt
+    sequence bit-identical to the oracle's potential form."""
+    need_gpu()
+    s = I.turbulence(dims, seed=61, kpeak=1.0, mach=0.7, b0=(0.3, 0.1, 0.2))
+    l = s.pop("_l")
+    h = l[0] / dims[0]
+    rng = np.random.default_rng(61)
+    a = {k: 0.05 * h * rng.standard_normal(s["rho"].shape) for k in POT}
+    a["b0"] = (0.3, 0.1, 0.2)
+    print("vecpot narrow", dims, tile, emf, flush=True)
+    g, tg, gd = gpu_run(s, a, dims, l, 3, emf=emf, tile=tile, zchunk=4)
+    o, ao = O.copy_state(s), copy_pot(a)
+    p = O.Params(*dims, *l, emf={"ec": O.EMF_EC, "e0": O.EMF_E0, "uct_hll": O.EMF_UCT_HLL}[emf])
+    t, dt, od = 0.0, 0.0, []
+    for _ in range(3):
+        t, dt, _ = O.step_vp(p, o, ao, t, dt, 1)
+        od.append(dt)
+    for f in FIELDS:
+        assert np.array_equal(g[f], o[f]), f
+    for f in POT:
+        assert np.array_equal(g[f], ao[f]), f
+    assert gd == od and tg == t
 
 
 def test_vecpot_fp32_is_refused():
