@@ -45,15 +45,17 @@ def test_ppm_fp64_every_tile(tile):
     assert gd == od
 
 
+@pytest.mark.parametrize("emf", ["ec", "uct_hll"])
 @pytest.mark.parametrize("dims", [(2, 9, 5), (7, 2, 3), (5, 6, 2), (1, 1, 33)])
-def test_ppm_fp64_narrow_boxes(dims):
-    """Extents of one and two cells: the three-cell halo wraps the box more than
-    once, exactly as the oracle's periodic index does."""
+def test_ppm_fp64_narrow_boxes(dims, emf):
+    """Extents of one and two cells: the three-cell halo (and, with UCT-HLL, the
+    six-face edge lines) wraps the box more than once, exactly as the oracle's
+    periodic index does."""
     need_gpu()
     s = I.turbulence(dims, seed=31, kpeak=1.0, mach=0.7, b0=(0.3, 0.1, 0.2))
     l = s.pop("_l")
-    print("ppm narrow", dims, flush=True)
-    g, o, gd, od, _ = run_both(s, dims, 3, l=l, per_step=True, recon="ppm", zchunk=2)
+    print("ppm narrow", dims, emf, flush=True)
+    g, o, gd, od, _ = run_both(s, dims, 3, l=l, per_step=True, recon="ppm", zchunk=2, emf=emf)
     assert bit_equal(g, o)
     assert gd == od
 
@@ -102,6 +104,21 @@ def test_ppm_fp32_within_tolerance(riemann):
                              integrator="rk3")
     st = _group_stats(g, o)
     print("ppm fp32 (max rel, l2 rel, fraction > 1e-5)", riemann, st)
+    for name, (mx, l2, frac) in st.items():
+        assert l2 <= 2e-6 and mx <= 2e-4 and frac <= 1e-3, (name, mx, l2, frac)
+
+
+@pytest.mark.parametrize("emf", ["e0", "arith", "uct_hll"])
+def test_ppm_fp32_other_emf_schemes(emf):
+    """FP32 PPM with the corner-EMF schemes that take no upwind decision, on the
+    same Orszag-Tang run: held to the same PPM bounds as with E^c."""
+    need_gpu()
+    s = I.to_float32_exact(I.orszag_tang(32))
+    print("ppm fp32", emf, flush=True)
+    g, o, _, _, _ = run_both(s, (32, 32, 32), 5, precision="fp32", recon="ppm", integrator="rk3",
+                             emf=emf)
+    st = _group_stats(g, o)
+    print("ppm fp32 (max rel, l2 rel, fraction > 1e-5)", emf, st)
     for name, (mx, l2, frac) in st.items():
         assert l2 <= 2e-6 and mx <= 2e-4 and frac <= 1e-3, (name, mx, l2, frac)
 
