@@ -19,7 +19,8 @@ def copy_pot(a):
 
 
 @pytest.mark.parametrize("integ,emf", [(O.RK2, O.EMF_EC), (O.RK3, O.EMF_EC),
-                                       (O.RK2, O.EMF_UCT_HLL)])
+                                       (O.RK2, O.EMF_UCT_HLL), (O.RK2, O.EMF_E0),
+                                       (O.RK3, O.EMF_ARITH)])
 def test_equivalent_to_face_update(integ, emf):
     n = 16
     s, a = I.orszag_tang_3d(n, potential=True)
