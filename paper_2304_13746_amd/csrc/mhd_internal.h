@@ -105,6 +105,32 @@ hipError_t stage_f32_hllc(const BatchArgs& b, int tile, int recon, hipStream_t s
 constexpr int kVpotBlock = 256;
 hipError_t vpot_update_f64(const BatchArgs& b, hipStream_t st);
 hipError_t vpot_curl_f64(const BatchArgs& b, hipStream_t st);
+// Cell (i, j, k) of the linear index c = (k ny + j) nx + i of a box with
+// plane = nx ny cells per plane (at most 2^24) and n cells in all; 32-bit
+// division when n < 2^31 (a uniform branch: one box per block).
+__host__ __device__ __forceinline__ void cell_ijk(long long c, int nx, long long plane, long long n,
+                                                  int& i, int& j, int& k) {
+  unsigned r;
+  if (n <= 0x7fffffffLL) {
+    const unsigned cu = (unsigned)c, p = (unsigned)plane;
+    k = (int)(cu / p);
+    r = cu - (unsigned)k * p;
+  } else {
+    k = (int)(c / plane);
+    r = (unsigned)(c - (long long)k * plane);
+  }
+  j = (int)(r / (unsigned)nx);
+  i = (int)(r - (unsigned)j * (unsigned)nx);
+}
+
+// v wrapped periodically into [0, n), for v within a few n of that range
+// (stencil offsets, also on boxes one or two cells wide).
+__host__ __device__ __forceinline__ int wrap_index(int v, int n) {
+  while (v < 0) v += n;
+  while (v >= n) v -= n;
+  return v;
+}
+
 // UCT-HLL after a stage launch: the edge EMFs from the face data the stage
 // kernel exported, then the face-field update B_dst = w (B_src - dt curl E) +
 // w0 B_base.  ba.start[] counts blocks of kUctBlock cells.

@@ -102,13 +102,12 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   const long long plane = (long long)nx * ny;
   const long long c = (long long)(blockIdx.x - ba.start[box]) * kUctBlock + threadIdx.x;
   if (c >= plane * nz) return;
-  const int i = (int)(c % nx);
-  const int j = (int)((c / nx) % ny);
-  const int k = (int)(c / plane);
+  int i, j, k;
+  cell_ijk(c, nx, plane, plane * nz, i, j, k);
   const long long row = c - i, col = c - (long long)j * nx, pil = c - (long long)k * plane;
-  auto xi = [&](int di) { return row + ((i + di) % nx + nx) % nx; };
-  auto yj = [&](int dj) { return col + (long long)(((j + dj) % ny + ny) % ny) * nx; };
-  auto zk = [&](int dk) { return pil + (long long)(((k + dk) % nz + nz) % nz) * plane; };
+  auto xi = [&](int di) { return row + wrap_index(i + di, nx); };
+  auto yj = [&](int dj) { return col + (long long)wrap_index(j + dj, ny) * nx; };
+  auto zk = [&](int dk) { return pil + (long long)wrap_index(k + dk, nz) * plane; };
   const int si = ba.src[box];
   const R* bx = static_cast<const R*>(d->buf[si][F_BX]);
   const R* by = static_cast<const R*>(d->buf[si][F_BX + 1]);
@@ -161,9 +160,8 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_ct(BatchArgs ba) {
   const long long plane = (long long)nx * ny;
   const long long c = (long long)(blockIdx.x - ba.start[box]) * kUctBlock + threadIdx.x;
   if (c >= plane * nz) return;
-  const int i = (int)(c % nx);
-  const int j = (int)((c / nx) % ny);
-  const int k = (int)(c / plane);
+  int i, j, k;
+  cell_ijk(c, nx, plane, plane * nz, i, j, k);
   const long long cxp = c - i + (i + 1 == nx ? 0 : i + 1);
   const long long cyp = c + (long long)((j + 1 == ny ? 0 : j + 1) - j) * nx;
   const long long czp = c + (long long)((k + 1 == nz ? 0 : k + 1) - k) * plane;

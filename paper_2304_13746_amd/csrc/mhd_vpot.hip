@@ -57,9 +57,8 @@ __global__ void __launch_bounds__(kVpotBlock) k_vpot_curl(BatchArgs ba) {
   const long long plane = (long long)nx * ny;
   const long long c = (long long)(blockIdx.x - ba.start[box]) * kVpotBlock + threadIdx.x;
   if (c >= plane * nz) return;
-  const int i = (int)(c % nx);
-  const int j = (int)((c / nx) % ny);
-  const int k = (int)(c / plane);
+  int i, j, k;
+  cell_ijk(c, nx, plane, plane * nz, i, j, k);
   const long long cxp = c - i + (i + 1 == nx ? 0 : i + 1);
   const long long cyp = c + (long long)((j + 1 == ny ? 0 : j + 1) - j) * nx;
   const long long czp = c + (long long)((k + 1 == nz ? 0 : k + 1) - k) * plane;
