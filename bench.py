@@ -266,9 +266,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-box batched run")
     ap.add_argument("--no-next", action="store_true",
-                    help="skip the runs of the widened scheme options (RK3, LimO3, E^0, "
-                         "arithmetic EMF, vector-potential CT) and of the Sedov 512^3 hydro "
-                         "workload")
+                    help="skip the runs of the widened scheme options (RK3, LimO3, PPM, E^0, "
+                         "arithmetic and UCT-HLL EMFs, vector-potential CT), of the Sedov "
+                         "512^3 hydro workload and of the 512^3 turbulence box")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests in the served replay (0: skip; the full stream is 5000)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
@@ -378,6 +378,22 @@ def main():
                 print(f"# sedov 512^3 {riem} {prec}: {ms_step:.3f} ms/cycle", file=sys.stderr,
                       flush=True)
         del sed
+        # the 512^3 turbulence configuration (E(k) ~ k^-5/3 on 2 <= k <= 64, rms
+        # Mach 1, B = (0.1, 0.1, 0)) with the default scheme: the per-cell rate
+        # at eight times the cells of the headline box
+        print("# generating the 512^3 turbulence input", file=sys.stderr, flush=True)
+        c5 = I.turbulence(512, seed=2304, spectrum="kolmogorov", kmin=2.0, kmax=64.0, mach=1.0,
+                          b0=(0.1, 0.1, 0.0))
+        c5.pop("_l")
+        for prec in precs:
+            r = run_gpu(c5, prec, k, 1, args.tile, args.zchunk, n=512)
+            ms_step = r["ms_total"] / k
+            nxt[f"turb512_{prec}"] = {"value": 512 ** 3 / (ms_step * 1e-3),
+                                      "unit": "cell-updates/s", "ms_per_step": ms_step,
+                                      "stage_launch_ms": ms_step / 2, "rc": r["rc"]}
+            print(f"# turbulence 512^3 {prec}: {ms_step:.3f} ms/cycle", file=sys.stderr,
+                  flush=True)
+        del c5
         line["next_rows"] = nxt
     if not args.no_batch:
         line["batched"] = batched_c3()
