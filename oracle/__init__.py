@@ -78,6 +78,8 @@ def lib():
         L.orc_step.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, C.c_int, C.c_double]
         L.orc_diagnostics.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp]
         L.orc_mass_flux.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, dp]
+        L.orc_ec_tie_spread.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.c_double, dp, dp,
+                                        dp]
         L.orc_step_vp.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.POINTER(_Vpot), dp, dp,
                                   C.c_int, C.c_double]
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
@@ -168,6 +170,18 @@ def mass_flux(p: Params, s: dict):
     rc = lib().orc_mass_flux(C.byref(p.c()), C.byref(_cstate(p, s)), *[_dptr(a) for a in out])
     if rc != OK:
         raise RuntimeError(f"orc_mass_flux failed: {rc}")
+    return out
+
+
+def ec_tie_spread(p: Params, s: dict, band: float):
+    """Per edge (sx at (i, j-1/2, k-1/2), sy at (i-1/2, j, k-1/2), sz at
+    (i-1/2, j-1/2, k)): how far the E^c corner EMF of state s can move when the
+    upwind switches whose |mass flux| <= band take another side."""
+    out = [np.zeros((p.nz, p.ny, p.nx)) for _ in range(3)]
+    rc = lib().orc_ec_tie_spread(C.byref(p.c()), C.byref(_cstate(p, s)), float(band),
+                                 *[_dptr(a) for a in out])
+    if rc != OK:
+        raise RuntimeError(f"orc_ec_tie_spread failed: {rc}")
     return out
 
 

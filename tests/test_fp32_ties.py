@@ -47,3 +47,34 @@ def test_tie_mask_marks_only_near_zero_mass_flux():
     want = set(range(5 - TIE_DILATE - 1, 5 + TIE_DILATE + 1)) | \
         set(range(21 - TIE_DILATE - 1, 21 + TIE_DILATE + 1))
     assert {5, 21} <= marked <= want
+
+
+def test_tie_spread_bounds_the_e0_difference():
+    """E^0 is E^c with every upwind switch at its tie value (the mean of the two
+    candidates), so at every edge |E^c - E^0| is at most half of the spread the
+    oracle helper reports with every switch counted (band = infinity).  One Euler
+    stage with each scheme therefore differs, face by face, by at most the
+    face-field bound built from that spread, and the bound is reached within a
+    small factor somewhere (it is not vacuous).  A wrong edge or neighbour index
+    in the helper or in the bound breaks this."""
+    from gpu_util import ec_field_slack
+    n = 16
+    s = I.turbulence(n, seed=5, kpeak=2.0, mach=0.9, b0=(0.2, -0.1, 0.15))
+    l = s.pop("_l")
+    dt = 0.3 / O.max_invdt(O.Params(n, n, n, *l), s)
+    out = {}
+    for emf in (O.EMF_EC, O.EMF_E0):
+        p = O.Params(n, n, n, *l, integrator=O.EULER, emf=emf)
+        u = O.copy_state(s)
+        O.step(p, u, 0.0, dt, 1)
+        out[emf] = u
+    slack = ec_field_slack(O.Params(n, n, n, *l), s, dt, band=np.inf)
+    ratio = 0.0
+    for f in ("bx", "by", "bz"):
+        d = np.abs(out[O.EMF_EC][f] - out[O.EMF_E0][f])
+        assert np.all(d <= 0.5 * slack[f] * (1 + 1e-12) + 1e-15)
+        ratio = max(ratio, float(np.max(d / (0.5 * slack[f] + 1e-300))))
+    assert ratio > 0.3
+    # the fluid is untouched by the corner EMFs within the stage
+    for f in ("rho", "mx", "my", "mz", "en"):
+        assert np.array_equal(out[O.EMF_EC][f], out[O.EMF_E0][f])

@@ -49,3 +49,21 @@ def test_uniform_state_counts_no_limiter_divisions(opcount, tmp_path):
     h = count(opcount, tmp_path, s, 8, ("hll",))
     # HLL: per face 2 x (1/rho in the fast speed) + 1/(S_R - S_L) = 3; 3 faces; S1: 1
     assert h["div"] == 10.0
+
+
+def test_repeated_slope_work_is_the_lower_face_reconstruction(opcount, tmp_path):
+    """The count without repeated work drops, per cell, direction and
+    reconstructed variable, the lower-face pass over differences and slope the
+    upper face already formed: on a uniform state (zero differences, van Leer
+    returns 0 after its one product) that pass is 2 differences + 1 product +
+    1 halving + 1 subtraction = 5 operations, for 7 variables and 3 directions."""
+    s = I.assemble(1.0, 0.1, 0.2, 0.3, 0.6, 0.2, 0.1, 0.05, 5.0 / 3.0, shape=(8, 8, 8))
+    h = count(opcount, tmp_path, s, 8, ("hll",))
+    assert h["repeated"] == 5 * 7 * 3
+    assert h["method_flops"] == pytest.approx(h["flops"] - h["repeated"], abs=0.01)
+    t = I.turbulence(16, seed=2304, kpeak=4.0, mach=0.5, b0=(0.2, 0.0, 0.0))
+    t.pop("_l")
+    d = count(opcount, tmp_path, t, 16)
+    # with non-zero slopes the repeated pass also holds van Leer's remaining
+    # product, sum and division: between 5 and 8 operations per variable
+    assert 5 * 21 < d["repeated"] <= 8 * 21
