@@ -32,13 +32,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, the same
-# for FP64 and non-packed FP32 (the kernels are compiled without packed FP32).
-ALU_PEAK_TFLOPS = 78.6
+# Vector-ALU lane-operation rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13
+# lane-ops/s, the same for FP64 and non-packed FP32 (packed FP32 is not used).
+LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+# Flop ceilings of the two builds: FP64 is compiled without fused multiply-add
+# (every flop is one lane-op: 39.3 TFLOP/s); FP32 contracts multiply-adds (an
+# FMA is two flops: 78.6 TFLOP/s at most).
+ALU_PEAK_TFLOPS = {"fp64": LANE_OPS_PER_S / 1e12, "fp32": 2 * LANE_OPS_PER_S / 1e12}
 # Algorithmic floating-point operations (add/sub, mul, div, sqrt) per cell and
 # stage of this method on this 256^3 input with HLLD, counted on the oracle by
-# oracle/opcount.cpp: 611.7 add/sub + 647.8 mul + 46.0 div + 18.0 sqrt.
-FLOPS_PER_CELL_STAGE = 1323.46
+# oracle/opcount.cpp ("method_flops": every difference, slope, face state,
+# Riemann solve and update formed once; the oracle's repeated lower-face slope
+# work, 131.2 per cell, is left out).
+FLOPS_PER_CELL_STAGE = 1192.30
 N = 256
 METRIC = "MHD cell-updates/s at 256^3 (FP64 vs FP32, %HBM peak); batched p50/p99 latency"
 
@@ -51,9 +57,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(precision: str):
-    """HBM bytes per stage launch from the committed rocprofv3 counter summary,
-    or None if the summary is missing or was taken on other kernel sources."""
+def _profile(precision: str):
+    """The committed rocprofv3 counter summary of the stage kernel, or None if it
+    is missing or was taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"stage_kernel_256_{precision}_counters.md")
     if not os.path.exists(path):
         return None
@@ -61,13 +67,27 @@ def counter_traffic(precision: str):
     m = re.search(r"kernel source hash: ([0-9a-f]+)", txt)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(r"HBM bytes per stage launch \(scaled\): ([0-9.eE+]+)", txt)
+    return txt
+
+
+def counter_traffic(precision: str):
+    """HBM bytes per stage launch from the counter summary (None if stale)."""
+    txt = _profile(precision)
+    m = re.search(r"HBM bytes per stage launch \(scaled\): ([0-9.eE+]+)", txt or "")
     return float(m.group(1)) if m else None
+
+
+def valu_per_cell(precision: str):
+    """VALU lane-instructions per cell and stage launch (mean of the RK2 stage-1
+    and stage-2 kernels) from the counter summary (None if stale)."""
+    txt = _profile(precision)
+    rows = re.findall(r"^\| mode [01] \|[^|]*\|[^|]*\| ([0-9.]+) \|", txt or "", re.M)
+    return sum(float(v) for v in rows) / len(rows) if len(rows) == 2 else None
 
 
 def run_gpu(state, precision: str, steps: int, warmup: int, tile: int = 0, zchunk: int = 0,
             integrator: str = "rk2", emf: str = "ec", recon: str = "plm", n: int = N,
-            riemann: str = "hlld", potential=None):
+            riemann: str = "hlld", potential=None, diagnostics: bool = False):
     import torch
 
     from paper_2304_13746_amd.box import MHDBox
@@ -78,6 +98,7 @@ def run_gpu(state, precision: str, steps: int, warmup: int, tile: int = 0, zchun
     if potential:
         state = dict(state, ax=potential["ax"], ay=potential["ay"], az=potential["az"])
     box.set_state(state)
+    d0 = box.diagnostics() if diagnostics else None
     box.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -90,80 +111,181 @@ def run_gpu(state, precision: str, steps: int, warmup: int, tile: int = 0, zchun
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     _, t, dt, rc = box.get_state(check=False)
+    out = {"ms_total": ms, "wall_s": wall, "t": t, "dt_next": dt, "rc": rc}
+    if diagnostics:
+        out["diagnostics"] = diag_drift(d0, box.diagnostics(), warmup + steps, t)
     box.close()
-    return {"ms_total": ms, "wall_s": wall, "t": t, "dt_next": dt, "rc": rc}
+    return out
+
+
+def diag_drift(d0, d1, cycles, t):
+    """Conserved totals (compensated FP64 sums on the GPU) before and after the
+    run: drift of mass and energy relative to their totals, of momentum and the
+    mean field relative to the mass and field totals' scale, and div B."""
+    bscale = max(float(np.max(np.abs(d0["bflux"]))), 1e-300)
+    return {"cycles": cycles, "t": t,
+            "mass_rel_drift": float(f"{(d1['mass'] - d0['mass']) / d0['mass']:.3e}"),
+            "energy_rel_drift": float(f"{(d1['energy'] - d0['energy']) / d0['energy']:.3e}"),
+            "momentum_drift": [float(f"{v:.3e}") for v in (d1["mom"] - d0["mom"])],
+            "mean_field_rel_drift": float(f"{float(np.max(np.abs(d1['bflux'] - d0['bflux']))) / bscale:.3e}"),
+            "divb_max_before": float(f"{d0['divb_max']:.3e}"),
+            "divb_max_after": float(f"{d1['divb_max']:.3e}"),
+            "divb_rms_after": float(f"{d1['divb_rms']:.3e}"), "status": d1["status"]}
 
 
 def roofline(precision: str, launch_ms: float):
     """Roofline of the stage kernel from its measured average launch duration.
-    The kernel is bound by vector ALU work (algorithmic flops per cell and stage
-    x cells per launch); the HBM view of the same launch (20 state words per
-    cell on average: 16 in stage 1, 24 in stage 2) is reported beside it."""
+    The method's bound is HBM bandwidth: per cell a stage launch moves 20 state
+    words on average (stage 1 reads 8 and writes 8, stage 2 reads 16 and writes
+    8), i.e. 160 B (FP64) or 80 B (FP32) against 8 TB/s.  Beside it: the
+    counter-measured traffic of the launch (copy-calibrated rocprofv3
+    FETCH/WRITE), the algorithmic flop rate against the build's ALU ceiling,
+    and the VALU issue floor from the counted lane-instructions."""
     word = 8 if precision == "fp64" else 4
     cells = N ** 3
     launch_s = launch_ms * 1e-3
-    flops_per_launch = FLOPS_PER_CELL_STAGE * cells
-    tflops = flops_per_launch / launch_s / 1e12
     bytes_per_launch = 20 * word * cells
     gbs = bytes_per_launch / launch_s / 1e9
     traffic = counter_traffic(precision)
-    return {"bound": "alu", "achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
-            "traffic": None if traffic is None else round(traffic / 1e9, 4),
-            "traffic_unit": "GB per stage launch (rocprofv3 FETCH/WRITE, copy-calibrated)",
-            "algorithmic_flops_per_launch": round(flops_per_launch),
-            "launch_ms": round(launch_ms, 4),
-            "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "algorithmic_bytes_per_launch": bytes_per_launch}}
+    flops = FLOPS_PER_CELL_STAGE * cells
+    tflops = flops / launch_s / 1e12
+    peak = ALU_PEAK_TFLOPS[precision]
+    out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "traffic": None if traffic is None else round(traffic / 1e9, 4),
+           "traffic_unit": "GB per stage launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
+                           "copy-calibrated)",
+           "traffic_ratio": None if traffic is None else round(traffic / bytes_per_launch, 3),
+           "algorithmic_bytes_per_launch": bytes_per_launch,
+           "launch_ms": round(launch_ms, 4),
+           "alu": {"achieved": round(tflops, 2), "peak": round(peak, 1), "unit": "TFLOP/s",
+                   "frac": round(tflops / peak, 4),
+                   "algorithmic_flops_per_cell_stage": FLOPS_PER_CELL_STAGE,
+                   "ceiling": "FP64 without fused multiply-add: 1 flop per lane-op"
+                              if precision == "fp64" else "FP32 with fused multiply-add"}}
+    v = valu_per_cell(precision)
+    if v is not None:
+        floor_ms = v * cells / LANE_OPS_PER_S * 1e3
+        out["valu"] = {"lane_instructions_per_cell_stage": round(v, 1),
+                       "issue_floor_ms": round(floor_ms, 4),
+                       "issue_frac": round(floor_ms / launch_ms, 4)}
+    return out
 
 
 CPU_CYCLES = 10  # about 10-15 s of oracle work on 16 host cores
+CPU_CYCLES_1T = 1  # one cycle (about 15-20 s) on one thread
 
 
 def cpu_baseline(state):
     """The FP64 oracle on the host cores: CPU_CYCLES RK2 cycles of the same 256^3
-    input (after its first-dt pre-pass), reported as cell-updates/s."""
+    input (after its first-dt pre-pass) on all OpenMP threads, and CPU_CYCLES_1T
+    cycles on one thread, reported as cell-updates/s."""
     import oracle as O
 
     s = O.copy_state(state)
     p = O.Params(N, N, N)
-    mi = O.max_invdt(p, s)
+    dt0 = 0.3 / O.max_invdt(p, s)
+    cores = O.num_threads()
     t0 = time.perf_counter()
-    O.step(p, s, 0.0, 0.3 / mi, CPU_CYCLES)
+    O.step(p, s, 0.0, dt0, CPU_CYCLES)
     el = time.perf_counter() - t0
+    print(f"# oracle, {cores} threads: {CPU_CYCLES} cycles in {el:.1f} s", file=sys.stderr, flush=True)
+    one = O.copy_state(state)
+    O.set_num_threads(1)
+    t0 = time.perf_counter()
+    O.step(p, one, 0.0, dt0, CPU_CYCLES_1T)
+    el1 = time.perf_counter() - t0
+    O.set_num_threads(cores)
+    del one
+    print(f"# oracle, 1 thread: {CPU_CYCLES_1T} cycle in {el1:.1f} s", file=sys.stderr, flush=True)
     return {"value": round(CPU_CYCLES * N ** 3 / el, 1), "unit": "cell-updates/s",
-            "cores": O.num_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"{CPU_CYCLES} RK2 cycles of the same 256^3 FP64 input ({el:.1f} s, OpenMP)",
+            "single_thread": {"value": round(CPU_CYCLES_1T * N ** 3 / el1, 1),
+                              "unit": "cell-updates/s", "cores": 1,
+                              "sample": f"{CPU_CYCLES_1T} RK2 cycle of the same input ({el1:.1f} s)"},
             "error_vs_oracle": errors_vs_oracle(state, s)}
 
 
+GROUPS = {"rho": ("rho",), "momentum": ("mx", "my", "mz"), "energy": ("en",),
+          "field": ("bx", "by", "bz")}
+
+
+def _group_errors(g, ref):
+    e = {}
+    for name, fs in GROUPS.items():
+        den = max(float(np.max(np.abs(ref[f]))) for f in fs)
+        num = max(float(np.max(np.abs(g[f] - ref[f]))) for f in fs)
+        l2 = math.sqrt(sum(float(np.sum((g[f] - ref[f]) ** 2)) for f in fs) /
+                       sum(float(np.sum(ref[f] ** 2)) for f in fs))
+        e[name] = {"max_rel": float(f"{num / den:.3e}"), "l2_rel": float(f"{l2:.3e}")}
+    return e
+
+
 def errors_vs_oracle(state, ref):
-    """Errors of the GPU results after the same cycles against the oracle's:
-    FP64 (expected bit-identical) and FP32 (input rounded to FP32 by the
-    library), per quantity as max|gpu - oracle| / max|oracle| and as the ratio
-    of L2 norms."""
+    """Errors of the GPU results after CPU_CYCLES cycles against the oracle's,
+    per quantity as max|gpu - oracle| / max|oracle| and as the ratio of L2
+    norms.  FP64 is compared with the oracle run above (expected bit-identical).
+    FP32 starts from the input rounded to FP32 and is compared with the oracle
+    run from that rounded input; its last cycle is also checked stage by stage
+    (each stage of the GPU against the oracle's stage applied to the GPU's own
+    stage input with the GPU's step; face fields allowed the E^c upwind-tie
+    slack of that stage: the spread of the corner EMF over the upwind switches
+    whose mass flux lies within 1e-5 of the largest one of zero)."""
+    import oracle as O
+    from paper_2304_13746_amd import inputs as I
     from paper_2304_13746_amd.box import MHDBox
 
-    groups = {"rho": ("rho",), "momentum": ("mx", "my", "mz"), "energy": ("en",),
-              "field": ("bx", "by", "bz")}
     out = {}
-    for prec in ("fp64", "fp32"):
-        box = MHDBox(N, N, N, precision=prec)
-        box.set_state(state)
-        box.step(CPU_CYCLES)
-        g, _, _, _ = box.get_state_numpy()
-        box.close()
-        e = {}
-        for name, fs in groups.items():
-            den = max(float(np.max(np.abs(ref[f]))) for f in fs)
-            num = max(float(np.max(np.abs(g[f] - ref[f]))) for f in fs)
-            l2 = math.sqrt(sum(float(np.sum((g[f] - ref[f]) ** 2)) for f in fs) /
-                           sum(float(np.sum(ref[f] ** 2)) for f in fs))
-            e[name] = {"max_rel": float(f"{num / den:.3e}"), "l2_rel": float(f"{l2:.3e}")}
-        if prec == "fp64":
-            e["bit_identical"] = all(np.array_equal(g[f], ref[f]) for f in ref)
-        out[prec] = e
+    box = MHDBox(N, N, N, precision="fp64")
+    box.set_state(state)
+    box.step(CPU_CYCLES)
+    g, _, _, _ = box.get_state_numpy()
+    box.close()
+    e = _group_errors(g, ref)
+    e["bit_identical"] = all(np.array_equal(g[f], ref[f]) for f in ref)
+    out["fp64"] = e
+    del g
+    s32 = I.to_float32_exact(state)
+    p = O.Params(N, N, N)
+    box = MHDBox(N, N, N, precision="fp32")
+    box.set_state(s32)
+    box.step(CPU_CYCLES - 1)
+    x0, _, dt, _ = box.get_state_numpy()
+    box.step(1)
+    x1 = box.get_stage_output(1)
+    g, _, _, _ = box.get_state_numpy()
+    box.close()
+    ref32 = O.copy_state(s32)
+    O.step(p, ref32, 0.0, 0.0, CPU_CYCLES)
+    e = _group_errors(g, ref32)
+    e["input"] = "rounded to FP32; oracle run from the rounded input"
+    del ref32
+    stages = []
+    for xin, y, w, w0 in ((x0, x1, 1.0, 0.0), (x1, g, 0.5, 0.5)):
+        pe = O.Params(N, N, N, integrator=O.EULER)
+        want = O.copy_state(xin)
+        O.step(pe, want, 0.0, dt, 1)
+        if w0:
+            want = {f: w * want[f] + w0 * x0[f] for f in O.FIELDS}
+        sx, sy, sz = O.ec_tie_spread(p, xin, -1e-5)
+        tx = ty = tz = dt * N
+        up = lambda a, ax: np.roll(a, -1, axis=ax)
+        slack = {"bx": w * (ty * (up(sz, 1) + sz) + tz * (up(sy, 0) + sy)),
+                 "by": w * (tz * (up(sx, 0) + sx) + tx * (up(sz, 2) + sz)),
+                 "bz": w * (tx * (up(sy, 2) + sy) + ty * (up(sx, 1) + sx))}
+        st = {f: float(np.max(np.abs(y[f] - want[f]) / np.abs(want[f]))) for f in ("rho", "en")}
+        ms = max(float(np.max(np.abs(want[f]))) for f in ("mx", "my", "mz"))
+        st["momentum"] = max(float(np.max(np.abs(y[f] - want[f]))) for f in ("mx", "my", "mz")) / ms
+        bs = max(float(np.max(np.abs(want[f]))) for f in ("bx", "by", "bz"))
+        st["field"] = max(float(np.max(np.abs(y[f] - want[f]))) for f in ("bx", "by", "bz")) / bs
+        st["field_beyond_tie_slack"] = max(
+            float(np.max(np.abs(y[f] - want[f]) - slack[f])) for f in ("bx", "by", "bz")) / bs
+        stages.append({k: float(f"{v:.3e}") for k, v in st.items()})
+    e["last_cycle_stagewise"] = {"stage1": stages[0], "stage2": stages[1],
+                                 "norms": "rho, en element-wise relative; momentum, field "
+                                          "max-abs over the largest value"}
+    out["fp32"] = e
     return out
 
 
@@ -245,15 +367,21 @@ def served_c4(nreq: int, precision: str = "fp32", rate: float = 200.0):
     budget = int(min(0.8 * free, 64 << 30))
     be = GpuBackend(precision=precision)
     reqs = poisson_requests(nreq, rate=rate, seed=2304)
-    for e in EDGES:  # initial states resident on the GPU before the clock starts
+    for e in EDGES:  # base states resident on the GPU before the clock starts
         for init in ("ot", "turb"):
-            from paper_2304_13746_amd.serve import Request
-            be.initial_state(Request(-1, 0.0, e, 1, init, 0))
+            be.base_state(e, init)
     torch.cuda.synchronize()
-    st = Server(be, budget_bytes=budget, max_active=64, epoch_steps=10).run(reqs)
+    def progress(done, total):  # a line every 500 retired requests
+        if done // 500 != progress.last:
+            progress.last = done // 500
+            print(f"# served {precision}: {done}/{total}", file=sys.stderr, flush=True)
+    progress.last = 0
+    st = Server(be, budget_bytes=budget, max_active=64, epoch_steps=10).run(reqs, progress=progress)
     s = st.summary()
-    s.update({"workload": f"{nreq} Poisson requests at {rate:g}/s, edges {list(EDGES)}, 10-200 RK2 "
-                          f"cycles, OT/turbulence, {precision.upper()}, HBM budget {budget / 2**30:.0f} GiB",
+    s.update({"workload": f"{nreq} Poisson requests at {rate:g}/s (the first {nreq} of the seeded "
+                          f"5000-request stream), edges {list(EDGES)}, 10-200 RK2 cycles, "
+                          f"OT/turbulence with per-request seeded translations, {precision.upper()}, "
+                          f"HBM budget {budget / 2**30:.0f} GiB",
               "precision": precision})
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
 
@@ -269,8 +397,11 @@ def main():
                     help="skip the runs of the widened scheme options (RK3, LimO3, PPM, E^0, "
                          "arithmetic and UCT-HLL EMFs, vector-potential CT), of the Sedov "
                          "512^3 hydro workload and of the 512^3 turbulence box")
-    ap.add_argument("--serve-requests", type=int, default=300,
-                    help="requests in the served replay (0: skip; the full stream is 5000)")
+    ap.add_argument("--serve-requests", type=int, default=5000,
+                    help="requests of the FP32 served replay (0: skip; the full stream is 5000)")
+    ap.add_argument("--serve-requests-fp64", type=int, default=800,
+                    help="requests of the FP64 served replay: the first ones of the same stream "
+                         "(0: skip)")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
@@ -307,10 +438,10 @@ def main():
         # launches (a few microseconds) are charged to them, conservatively
         results[prec] = {"value": N ** 3 / (ms_step * 1e-3), "ms_per_step": ms_step,
                          "roofline": roofline(prec, ms_step / 2.0), "rc": r["rc"]}
+        rf = results[prec]["roofline"]
         print(f"# {prec}: {ms_step:.3f} ms/cycle, {results[prec]['value']:.4e} cell-updates/s, "
-              f"stage kernel {results[prec]['roofline']['achieved']:.2f} TFLOP/s, "
-              f"{results[prec]['roofline']['hbm']['achieved']:.0f} GB/s algorithmic, rc={r['rc']}",
-              file=sys.stderr, flush=True)
+              f"stage kernel {rf['achieved']:.0f} GB/s algorithmic ({rf['frac']:.3f} of HBM), "
+              f"{rf['alu']['achieved']:.2f} TFLOP/s, rc={r['rc']}", file=sys.stderr, flush=True)
     main_prec = precs[0]
     m = results[main_prec]
     line = {
@@ -386,22 +517,39 @@ def main():
                           b0=(0.1, 0.1, 0.0))
         c5.pop("_l")
         for prec in precs:
-            r = run_gpu(c5, prec, k, 1, args.tile, args.zchunk, n=512)
+            r = run_gpu(c5, prec, k, 1, args.tile, args.zchunk, n=512, diagnostics=True)
             ms_step = r["ms_total"] / k
             nxt[f"turb512_{prec}"] = {"value": 512 ** 3 / (ms_step * 1e-3),
                                       "unit": "cell-updates/s", "ms_per_step": ms_step,
-                                      "stage_launch_ms": ms_step / 2, "rc": r["rc"]}
-            print(f"# turbulence 512^3 {prec}: {ms_step:.3f} ms/cycle", file=sys.stderr,
-                  flush=True)
+                                      "stage_launch_ms": ms_step / 2, "rc": r["rc"],
+                                      "diagnostics": r["diagnostics"]}
+            print(f"# turbulence 512^3 {prec}: {ms_step:.3f} ms/cycle, {r['diagnostics']}",
+                  file=sys.stderr, flush=True)
         del c5
+        # the paper's own performance problem (Sec. 5): the 3D Orszag-Tang vortex
+        # at the 256^3 per-GPU size of its node benchmarks, default scheme
+        ot = I.orszag_tang_3d(N)
+        for prec in precs:
+            r = run_gpu(ot, prec, k, 1, args.tile, args.zchunk)
+            ms_step = r["ms_total"] / k
+            nxt[f"ot3d256_{prec}"] = {"value": N ** 3 / (ms_step * 1e-3), "unit": "cell-updates/s",
+                                      "ms_per_step": ms_step, "stage_launch_ms": ms_step / 2,
+                                      "rc": r["rc"]}
+            print(f"# 3D Orszag-Tang 256^3 {prec}: {ms_step:.3f} ms/cycle", file=sys.stderr,
+                  flush=True)
+        del ot
         line["next_rows"] = nxt
     if not args.no_batch:
         line["batched"] = batched_c3()
         print(f"# batched: {line['batched']['value']:.4e} cell-updates/s, "
               f"{line['batched']['speedup_vs_sequential']}x vs sequential", file=sys.stderr, flush=True)
-    if args.serve_requests > 0:
-        line["served"] = [served_c4(args.serve_requests, p) for p in ("fp32", "fp64")]
-        for sv in line["served"]:
+    served = [(n, p) for n, p in ((args.serve_requests, "fp32"), (args.serve_requests_fp64, "fp64"))
+              if n > 0]
+    if served:
+        line["served"] = []
+        for nreq, prec in served:
+            sv = served_c4(nreq, prec)
+            line["served"].append(sv)
             print(f"# served {sv['precision']}: p50 {sv['p50_ms']} ms p99 {sv['p99_ms']} ms, "
                   f"{sv['cell_updates_per_s']:.3e} cell-updates/s", file=sys.stderr, flush=True)
     if not args.no_cpu:

@@ -131,8 +131,11 @@ typedef struct {
 size_t mhd_workspace_bytes(const mhd_params* params);
 
 /* Validate params and build a context on the borrowed workspace.  *out receives
- * the context (host memory owned by the library until mhd_destroy).  Errors:
- * MHD_ERR_INVALID_ARG, MHD_ERR_WORKSPACE, MHD_ERR_UNSUPPORTED. */
+ * the context (host memory owned by the library until mhd_destroy).  The box
+ * descriptor is written into the workspace by a launch queued on the stream:
+ * the call does not synchronise (it sits on a serving loop's admission path).
+ * Errors: MHD_ERR_INVALID_ARG, MHD_ERR_WORKSPACE, MHD_ERR_UNSUPPORTED,
+ * MHD_ERR_HIP. */
 int mhd_create(const mhd_params* params, mhd_ctx** out);
 
 /* Copy the state from src (device arrays, see above) into the context and set the
@@ -150,6 +153,16 @@ int mhd_step(mhd_ctx* ctx, int nsteps, double t_stop);
  * next cycle.  Synchronises the stream.  Returns MHD_ERR_NONPHYSICAL (after the
  * copy) if a non-physical value was met since the last set_state. */
 int mhd_get_state(mhd_ctx* ctx, const mhd_state_view* dst, double* t, double* dt_next);
+
+/* Copy out an intermediate stage result of the last cycle (Sec. 2.7, Tab.
+ * weights): stage 1 is U_1 = S_dt(U^n) of an RK2 or RK3 cycle, stage 2 the
+ * combination U_2 = 1/4 S_dt(U_1) + 3/4 U^n of an RK3 cycle.  For checking a
+ * reduced-precision run stage by stage against a reference applied to the same
+ * stage input.  dst as for mhd_get_state.  MHD_ERR_INVALID_ARG if the
+ * integrator has no such stage or no cycle has run since mhd_set_state (or
+ * since mhd_tune, whose timed launches overwrite the stage buffer).
+ * Synchronises the stream. */
+int mhd_get_stage_output(mhd_ctx* ctx, int stage, const mhd_state_view* dst);
 
 /* Conserved totals with compensated FP64 sums and div B statistics of the current
  * state.  Synchronises the stream. */

@@ -98,6 +98,8 @@ def lib():
         L.orc_corner_emf_scheme.argtypes = [C.c_int] + [C.c_double] * 12
         L.orc_corner_emf_scheme.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -176,7 +178,8 @@ def mass_flux(p: Params, s: dict):
 def ec_tie_spread(p: Params, s: dict, band: float):
     """Per edge (sx at (i, j-1/2, k-1/2), sy at (i-1/2, j, k-1/2), sz at
     (i-1/2, j-1/2, k)): how far the E^c corner EMF of state s can move when the
-    upwind switches whose |mass flux| <= band take another side."""
+    upwind switches whose |mass flux| <= band take another side (band < 0:
+    |band| times the largest |mass flux| of s)."""
     out = [np.zeros((p.nz, p.ny, p.nx)) for _ in range(3)]
     rc = lib().orc_ec_tie_spread(C.byref(p.c()), C.byref(_cstate(p, s)), float(band),
                                  *[_dptr(a) for a in out])
@@ -270,3 +273,8 @@ def corner_emf_scheme(scheme, a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1,
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the following oracle calls (n > 0)."""
+    lib().orc_set_num_threads(int(n))

@@ -1039,7 +1039,8 @@ int orc_ec_tie_spread(const orc_params* p, const orc_state* s, double band, doub
                       double* sy, double* sz) {
   int rc = check_params(p);
   if (rc) return rc;
-  if (!s || !sx || !sy || !sz || !(band >= 0.0)) return ORC_ERR_INVALID_ARG;
+  /* band < 0: relative, |band| times the largest |mass flux| of the state */
+  if (!s || !sx || !sy || !sz || !(band == band)) return ORC_ERR_INVALID_ARG;
   grid_t g;
   grid_init(&g, p);
   work_t w;
@@ -1051,6 +1052,15 @@ int orc_ec_tie_spread(const orc_params* p, const orc_state* s, double band, doub
   double* const* fy = w.f[1];
   double* const* fz = w.f[2];
   double* out[3] = {sx, sy, sz};
+  if (band < 0.0) {
+    double m = 0.0;
+    for (int d = 0; d < 3; ++d)
+      for (long c = 0; c < g.n; ++c) {
+        double a = fabs(w.f[d][F_RHO][c]);
+        m = a > m ? a : m;
+      }
+    band = -band * m;
+  }
 #pragma omp parallel for schedule(static)
   for (int k = 0; k < g.nz; ++k) {
     int km = dn(k, g.nz);
@@ -1228,3 +1238,7 @@ int orc_diagnostics(const orc_params* p, const orc_state* s, double out[10]) {
 }
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+void orc_set_num_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}

@@ -74,7 +74,8 @@ int orc_step_vp(const orc_params* p, orc_state* s, orc_vpot* a, double* t, doubl
 int orc_mass_flux(const orc_params* p, const orc_state* s, double* fx, double* fy, double* fz);
 /* Test helper for reduced-precision comparisons: for every edge, how far the E^c
  * corner EMF of the state can move when the upwind switches whose |mass flux|
- * <= band take another side (a quarter of the sum of |L - R| over them). */
+ * <= band take another side (a quarter of the sum of |L - R| over them).  A
+ * negative band is relative: |band| times the largest |mass flux| of the state. */
 int orc_ec_tie_spread(const orc_params* p, const orc_state* s, double band, double* sx,
                       double* sy, double* sz);
 
@@ -90,8 +91,10 @@ int orc_step(const orc_params* p, orc_state* s, double* t, double* dt_next,
  * out[9] rms div B. */
 int orc_diagnostics(const orc_params* p, const orc_state* s, double out[10]);
 
-/* Threads the OpenMP loops use (the CPU-baseline report states it). */
+/* Threads the OpenMP loops use (the CPU-baseline report states it), and a way
+ * to change it (n > 0; for the single-thread baseline). */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* ---- single building blocks, exported so tests can pin them ---- */
 

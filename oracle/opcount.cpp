@@ -65,6 +65,7 @@ static inline bool isfinite_c(CD a) { return std::isfinite(a.v); }
 #include <string.h>
 // single-threaded: OpenMP pragmas are ignored without -fopenmp
 extern "C" int omp_get_max_threads(void) { return 1; }
+extern "C" void omp_set_num_threads(int) {}
 
 #define ORC_OPCOUNT_REPEATED RepeatedScope repeated_scope_;
 #define double CD

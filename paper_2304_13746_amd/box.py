@@ -141,6 +141,21 @@ class MHDBox:
             L.check(rc, "mhd_get_state")
         return out, t.value, dt.value, rc
 
+    def get_stage_output(self, stage: int = 1, numpy: bool = True) -> dict:
+        """The last cycle's stage-`stage` result (mhd_get_stage_output), as FP64
+        numpy arrays or, with numpy=False, as device tensors of the box's
+        precision (synchronises the box's stream)."""
+        with torch.cuda.stream(self.stream):
+            out = {f: torch.empty(self.shape, dtype=self.dtype, device=self.device)
+                   for f in self._fields()}
+        v = _view(out)
+        rc = self.lib.mhd_get_stage_output(self.ctx, int(stage), C.byref(v))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        L.check(rc, "mhd_get_stage_output")
+        if not numpy:
+            return out
+        return {f: out[f].double().cpu().numpy() for f in out}
+
     def get_state_numpy(self, check: bool = True):
         s, t, dt, rc = self.get_state(check)
         return {f: s[f].double().cpu().numpy() for f in s}, t, dt, rc

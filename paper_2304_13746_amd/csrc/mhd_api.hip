@@ -30,6 +30,7 @@ struct mhd_ctx {
   int lz;            // z-planes per work-group in effect
   int diag_blocks;
   int tiles;         // stage-kernel blocks for this box
+  int stages_valid;  // intermediate buffers hold the last cycle's stage results
 };
 
 namespace {
@@ -207,6 +208,15 @@ __global__ void k_diag_final(const double* part, int nblocks, double dv, double 
   for (int q = 0; q < 8; ++q) st_agent(&s->diag[q], (tot[q].s + tot[q].c) * dv);
   st_agent(&s->diag[8], m);
   st_agent(&s->diag[9], sqrt((tot[8].s + tot[8].c) / ncell));
+}
+
+// Copy a box descriptor (passed by value) into the workspace, with agent-scope
+// stores like the other values later kernels read (see Scalars).
+__global__ void k_put_desc(BoxDesc d, BoxDesc* dst) {
+  static_assert(sizeof(BoxDesc) % 8 == 0, "descriptor copied in 8-byte words");
+  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(&d);
+  unsigned long long* o = reinterpret_cast<unsigned long long*>(dst);
+  for (int w = threadIdx.x; w < (int)(sizeof(BoxDesc) / 8); w += blockDim.x) st_agent(o + w, s[w]);
 }
 
 int hip_fail(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_HIP; }
@@ -399,6 +409,7 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
       for (int i = 0; i < m; ++i) act[i]->cur = roles[i].dst;
     }
     if (launch_ctl(false, act, m, ts, st) != hipSuccess) return MHD_ERR_HIP;
+    for (int i = 0; i < m; ++i) act[i]->stages_valid = integ != MHD_EULER;
   }
   return MHD_OK;
 }
@@ -422,8 +433,10 @@ int choose_lz(int tile, int nx, int ny, int nz) {
 
 // Give c the launch shape (tile, zchunk; 0 = automatic): raise the dynamic-LDS
 // limit of the tile's kernels and rewrite the box descriptor on the device.
-// Synchronous: kernels in flight on c's stream may still read the old one.
-int apply_shape(mhd_ctx* c, int tile, int zchunk) {
+// With sync, wait for c's stream before (kernels in flight may still read the
+// old descriptor) and after the upload; without, the upload is only enqueued on
+// c's stream (a new context, whose descriptor nothing reads yet).
+int apply_shape(mhd_ctx* c, int tile, int zchunk, bool sync = true) {
   int tx, ty;
   if (!tile_dims(tile, &tx, &ty)) return MHD_ERR_INVALID_ARG;
   const mhd_params* p = &c->p;
@@ -452,9 +465,14 @@ int apply_shape(mhd_ctx* c, int tile, int zchunk) {
   d.sc = c->sc;
   d.uct = c->uct;
   d.ustride = (long long)(field_bytes(p) / c->elem);
-  if (hipStreamSynchronize(c->stream) != hipSuccess ||
-      hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess)
-    return MHD_ERR_HIP;
+  // the descriptor goes up as a kernel argument: no host buffer has to outlive
+  // the call and nothing waits for the stream
+  if (sync && hipStreamSynchronize(c->stream) != hipSuccess) return MHD_ERR_HIP;
+  hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, c->stream, d, c->desc);
+  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  // launches on other streams (batches, the tuner) read it right after a
+  // synchronous reshape
+  if (sync && hipStreamSynchronize(c->stream) != hipSuccess) return MHD_ERR_HIP;
   c->tile = tile;
   c->zchunk = zchunk;
   c->lz = lz;
@@ -567,7 +585,9 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   w += (size_t)nscratch_of(p) * fb;
   c->cur = 0;
   c->diag_blocks = kDiagBlocks;
-  if (apply_shape(c, tile, p->zchunk) != MHD_OK) {
+  // no host synchronisation on this path (contexts are created on a serving
+  // loop's admission path): the descriptor upload is queued on the stream
+  if (apply_shape(c, tile, p->zchunk, false) != MHD_OK) {
     free(c);
     return MHD_ERR_HIP;
   }
@@ -590,6 +610,7 @@ int mhd_set_state(mhd_ctx* c, const mhd_state_view* v, double t, double dt_next)
     if (!src[f] && !(vp && f >= 5 && f < 8)) return MHD_ERR_INVALID_ARG;
   const size_t bytes = (size_t)c->ncell * c->elem;
   c->cur = 0;
+  c->stages_valid = 0;
   for (int f = 0; f < c->nfield; ++f) {
     if (vp && f >= 5 && f < 8) continue;
     hipError_t e = hipMemcpyAsync(c->buf[0][f], src[f], bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -639,6 +660,24 @@ int mhd_get_state(mhd_ctx* c, const mhd_state_view* v, double* t, double* dt_nex
   if (t) *t = h.t;
   if (dt_next) *dt_next = h.dt_next;
   return h.status ? MHD_ERR_NONPHYSICAL : MHD_OK;
+}
+
+int mhd_get_stage_output(mhd_ctx* c, int stage, const mhd_state_view* v) {
+  if (!c || !v) return MHD_ERR_INVALID_ARG;
+  // RK2 and RK3 write stage s < last into buffer s (the state stays in buffer 0)
+  const int last = c->p.integrator == MHD_RK3 ? 3 : c->p.integrator == MHD_RK2 ? 2 : 1;
+  if (stage < 1 || stage >= last || !c->stages_valid || c->cur != 0) return MHD_ERR_INVALID_ARG;
+  void* dst[11];
+  fields_of(v, dst);
+  for (int f = 0; f < 8; ++f)
+    if (!dst[f]) return MHD_ERR_INVALID_ARG;
+  const int nf = c->nfield == 11 && dst[8] && dst[9] && dst[10] ? 11 : 8;
+  const size_t bytes = (size_t)c->ncell * c->elem;
+  for (int f = 0; f < nf; ++f) {
+    hipError_t e = hipMemcpyAsync(dst[f], c->buf[stage][f], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return MHD_ERR_HIP;
+  }
+  return hipStreamSynchronize(c->stream) == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
 int mhd_get_diagnostics(mhd_ctx* c, mhd_diag* out) {
@@ -763,10 +802,12 @@ int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_resul
         best_cap = cap;
       }
     }
+  // the timed launches wrote the second buffer
+  for (int i = 0; i < n; ++i) ctxs[i]->stages_valid = 0;
   if (rc == MHD_OK)
     for (int i = 0; i < n && rc == MHD_OK; ++i) rc = apply_shape(ctxs[i], best_tile, best_cap);
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   free(src);
   free(times);
   if (rc == MHD_OK && out) {

@@ -238,6 +238,32 @@ def sedov(n: int = 512, r_cells: float = 3.0, energy: float = 1.0, rho0: float =
     return assemble(rho0, z, z, z, p, z, z, z, gamma)
 
 
+def serving_base(edge: int, init: str) -> dict:
+    """Base initial data of a served box of this edge: Orszag-Tang ("ot", the
+    C1 form, density noise seed 2304) or turbulence ("turb", the 256^3
+    benchmark's recipe at this edge, seed 2304)."""
+    if init == "ot":
+        return orszag_tang(edge, seed=2304)
+    s = turbulence(edge, seed=2304, kpeak=4.0, mach=0.5)
+    s.pop("_l")
+    return s
+
+
+def request_shift(seed: int, edge: int) -> tuple:
+    """Periodic translation (sx, sy, sz), in cells, that a request's seed draws."""
+    rng = np.random.default_rng(seed)
+    return tuple(int(v) for v in rng.integers(0, edge, 3))
+
+
+def serving_state(edge: int, init: str, seed: int) -> dict:
+    """Initial data of one served request: its base field translated
+    periodically by the seeded shift (cell and face arrays move together, so
+    the discrete divergence stays zero); every request gets its own data at the
+    cost of a copy, which a server can do on the device."""
+    sx, sy, sz = request_shift(seed, edge)
+    return {k: np.roll(v, (sz, sy, sx), axis=(0, 1, 2)) for k, v in serving_base(edge, init).items()}
+
+
 def batch_boxes(nbox: int = 64, seed: int = 2304, emin: int = 16, emax: int = 128,
                 gamma: float = 5.0 / 3.0):
     """Batch of uneven periodic boxes: each edge 8 * round(e^u / 8) with

@@ -180,9 +180,11 @@ class Stats:
 
 
 class GpuBackend:
-    """libmhd backend: one context per request on a torch workspace.  Initial
-    states are generated once per (edge, init) and kept on the GPU, so
-    admission costs a device-to-device copy."""
+    """libmhd backend: one context per request on a torch workspace.  Base
+    initial states are generated once per (edge, init) and kept on the GPU;
+    a request's own initial data is its base translated periodically by the
+    shift its seed draws (inputs.serving_state), so admission costs one
+    device-side copy."""
 
     def __init__(self, precision: str = "fp32", device: str = "cuda:0", riemann: str = "hlld",
                  initial_states: dict | None = None):
@@ -202,18 +204,19 @@ class GpuBackend:
         self._states = {} if initial_states is None else initial_states
         self._batches = {}
 
-    def initial_state(self, r: Request):
-        key = (r.edge, r.init)
+    def base_state(self, edge: int, init: str):
+        key = (edge, init)
         if key not in self._states:
-            if r.init == "ot":
-                s = self.I.orszag_tang(r.edge, seed=2304)
-            else:
-                s = self.I.turbulence(r.edge, seed=2304, kpeak=4.0, mach=0.5)
-                s.pop("_l")
+            s = self.I.serving_base(edge, init)
             dt = self.torch.float32 if self.precision == "fp32" else self.torch.float64
             self._states[key] = {k: self.torch.from_numpy(np.ascontiguousarray(v)).to(self.device, dt)
                                  for k, v in s.items()}
         return self._states[key]
+
+    def initial_state(self, r: Request):
+        sx, sy, sz = self.I.request_shift(r.seed, r.edge)
+        return {k: self.torch.roll(v, (sz, sy, sx), (0, 1, 2))
+                for k, v in self.base_state(r.edge, r.init).items()}
 
     def workspace_bytes(self, r: Request) -> int:
         return self._ws(r.edge, r.edge, r.edge, self.precision)

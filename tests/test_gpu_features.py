@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import (FIELDS, assert_fp32_close, bit_equal, gpu_box, max_rel, need_gpu, run_both,
-                      upwind_tie_cells)
+from gpu_util import (FIELDS, bit_equal, check_fp32_cycles, gpu_box, max_rel, need_gpu,
+                      run_both)
 from paper_2304_13746_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -71,18 +71,26 @@ def test_full_size_256_vecpot_fp64_bit_exact(turb256):
     assert tg == t and dg == dt
 
 
-def test_full_size_256_fp32(turb256):
-    """One FP32 cycle at 256^3 against the FP64 oracle on the rounded input:
-    1e-5 norm-wise relative, face fields near E^c upwind ties to the looser
-    bound (see gpu_util)."""
+@pytest.mark.timeout(600)
+def test_full_size_256_fp32_ten_cycles(turb256):
+    """Ten FP32 cycles at 256^3 from the FP32-rounded input, in the benchmark's
+    launch shape: every stage of every cycle against the oracle's stage applied
+    to the GPU's own input of that stage, with the GPU's step (density and
+    energy element-wise, momentum norm-wise to 1e-5; face fields to 1e-5 plus
+    the E^c tie slack of that stage), and each step against eq. (cfl) on the
+    GPU state.  The end-to-end difference from the oracle run on the rounded
+    input is printed."""
     need_gpu()
     s = I.to_float32_exact(turb256)
-    g, o, gd, od, _ = run_both(s, (256, 256, 256), 1, precision="fp32")
     p = O.Params(256, 256, 256)
-    near = upwind_tie_cells(p, s, 0.3 / O.max_invdt(p, s))
-    e = assert_fp32_close(g, o, near)
-    print("256^3 fp32 errors", e, "max rel", max_rel(g, o))
-    assert abs(gd[-1] - od[-1]) <= 1e-5 * od[-1]
+    box = gpu_box((256, 256, 256), precision="fp32")
+    box.set_state(s)
+    worst = check_fp32_cycles(box, p, 10)
+    g, _, _, _ = box.get_state_numpy()
+    box.close()
+    o = O.copy_state(s)
+    O.step(p, o, 0.0, 0.0, 10)
+    print("256^3 fp32, 10 cycles: worst stage errors", worst, "end-to-end max rel", max_rel(g, o))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -204,3 +212,45 @@ def test_t_stop_clips_last_step():
     box.step(2, t_stop=t_stop)
     g2, t5, _, _ = box.get_state_numpy()
     assert t5 == t4 and bit_equal(g1, g2)
+
+
+def test_stage_output_availability():
+    """mhd_get_stage_output returns the last cycle's stage result only when one
+    exists: not before a cycle, not for stages the integrator lacks, not after
+    the tuner's timed launches overwrote the buffer; in FP64 stage 1 of an RK2
+    cycle is bit-identical to the oracle's Euler stage."""
+    need_gpu()
+    from paper_2304_13746_amd import _lib as L
+    s = I.orszag_tang(16)
+    box = gpu_box((16, 16, 16))
+    box.set_state(s)
+    with pytest.raises(L.MHDError):
+        box.get_stage_output(1)
+    box.step(1)
+    x1 = box.get_stage_output(1)
+    _, t, _, _ = box.get_state_numpy()
+    with pytest.raises(L.MHDError):
+        box.get_stage_output(2)
+    want = O.copy_state(s)
+    O.step(O.Params(16, 16, 16, integrator=O.EULER), want, 0.0, t, 1)
+    assert bit_equal(x1, want)
+    import ctypes as C
+    arr = (C.c_void_p * 1)(box.ctx.value)
+    L.check(box.lib.mhd_tune(arr, 1, 1, None, None), "mhd_tune")
+    with pytest.raises(L.MHDError):
+        box.get_stage_output(1)
+    box.close()
+    eul = gpu_box((16, 16, 16), integrator="euler")
+    eul.set_state(s)
+    eul.step(1)
+    with pytest.raises(L.MHDError):
+        eul.get_stage_output(1)
+    eul.close()
+    rk3 = gpu_box((16, 16, 16), integrator="rk3")
+    rk3.set_state(s)
+    rk3.step(2)
+    rk3.get_stage_output(1)
+    rk3.get_stage_output(2)
+    with pytest.raises(L.MHDError):
+        rk3.get_stage_output(3)
+    rk3.close()

@@ -5,9 +5,10 @@ hold at any size.
   one RK2 cycle on the GPU with the default launch shape; the first step equals
   the oracle's eq. (cfl) step on the whole box; periodic windows around seeded
   sample points (and one across the periodic corner) run through the oracle
-  reproduce the GPU result in the window interiors, bit for bit in FP64 and to
-  1e-5 in FP32 (the window property itself is pinned on the CPU in
-  test_oracle_scheme.py).  20 cycles conserve mass, momentum, energy and the
+  reproduce the GPU result in the window interiors, bit for bit in FP64; in FP32
+  each stage of the GPU matches the oracle's stage on the GPU's own stage input
+  in the windows (1e-5, face fields plus the E^c tie slack; the window property
+  itself is pinned on the CPU in test_oracle_scheme.py).  20 cycles conserve mass, momentum, energy and the
   mean field to round-off and keep div B at round-off (compensated FP64 sums).
 * 512^3 Sedov-Taylor blast (B = 0) with HLLC and HLL: one RK2 cycle in the
   default launch shape; the step equals the oracle's, windows over the blast,
@@ -23,7 +24,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import FIELDS, assert_fp32_close, bit_equal, max_rel, need_gpu, upwind_tie_cells
+from gpu_util import (FIELDS, assert_stage_valid, bit_equal, ec_field_slack, max_rel, need_gpu,
+                      oracle_stage, stage_errors)
 from helpers import inner, oracle_window_cycle, take_window, window_index
 from paper_2304_13746_amd import inputs as I
 
@@ -69,6 +71,7 @@ def test_c5_512_one_cycle_sampled(c5_state, precision):
     box.step(1)
     g, t, _, rc = box.get_state()
     assert rc == 0
+    mid = box.get_stage_output(1, numpy=False) if precision == "fp32" else None
     p = O.Params(*dims)
     dt = 0.3 / O.max_invdt(p, s)
     print(f"512^3 {precision}: gpu dt {t!r} oracle dt {dt!r}", flush=True)
@@ -86,10 +89,17 @@ def test_c5_512_one_cycle_sampled(c5_state, precision):
         if precision == "fp64":
             assert bit_equal(got, ref), c
         else:
-            w = take_window(s, idx)
+            # stage by stage: the oracle's stage on the GPU's own stage input
             pw = O.Params(WIN, WIN, WIN, WIN / N5, WIN / N5, WIN / N5)
-            near = inner({"m": upwind_tie_cells(pw, w, t)})["m"]
-            assert_fp32_close(got, ref, near)
+            x0 = take_window(s, idx)
+            x1 = gpu_window(torch, mid, idx)
+            y = gpu_window(torch, g, idx)
+            for xin, out, w, w0 in ((x0, x1, 1.0, 0.0), (x1, y, 0.5, 0.5)):
+                want = oracle_stage(pw, xin, t, w, w0, x0)
+                slack = ec_field_slack(pw, xin, t, weight=w)
+                e = stage_errors(inner(out), inner(want), inner(slack))
+                print(c, w, e, flush=True)
+                assert_stage_valid(e)
     print(f"512^3 {precision}: worst window max rel {worst:.3e}")
     box.close()
 
@@ -186,8 +196,12 @@ def test_c3_batch_full_size_vs_oracle(precision):
         if precision == "fp64":
             assert bit_equal(g, o) and t == to, sp["dims"]
         else:
-            near = upwind_tie_cells(p, st, to)
-            e = assert_fp32_close(g, o, near)
-            worst = max(worst, e["b_near"], e["b_far"], e["rho"], e["mx"], e["en"])
+            # stage by stage, with the GPU's step, on the GPU's own stage input
+            x1 = bx.get_stage_output(1)
+            for xin, out, w, w0 in ((st, x1, 1.0, 0.0), (x1, g, 0.5, 0.5)):
+                want = oracle_stage(p, xin, t, w, w0, st)
+                e = stage_errors(out, want, ec_field_slack(p, xin, t, weight=w))
+                assert_stage_valid(e)
+                worst = max(worst, e["rho"], e["en"], e["m"], e["b_excess"])
             assert abs(t - to) <= 1e-5 * to
     print(f"64 boxes {precision}: worst max rel {worst:.3e}")

@@ -259,3 +259,27 @@ def test_maximum_extent_fp64(dims):
     g, o, gd, od, _ = run_both(s, dims, 2, l=l, per_step=True)
     assert bit_equal(g, o)
     assert gd == od
+
+
+@pytest.mark.parametrize("opts", [
+    {}, {"riemann": "hll"}, {"integrator": "rk3"}, {"recon": "limo3", "integrator": "rk3"},
+    {"emf": "e0"}, {"emf": "arith"}, {"emf": "uct_hll"},
+    {"recon": "limo3", "integrator": "rk3", "emf": "uct_hll"}],
+    ids=lambda o: "-".join(o.values()) or "default")
+def test_fp32_every_stage_valid(opts):
+    """FP32 on the noisy Orszag-Tang 32^3 input (rounded to FP32), 5 cycles, every
+    stage against the oracle's stage applied to the GPU's own stage input with
+    the GPU's step: density and energy element-wise and momentum norm-wise to
+    1e-5, face fields to 1e-5 plus the E^c tie slack (gpu_util); each step
+    against eq. (cfl) on the GPU state."""
+    need_gpu()
+    from gpu_util import check_fp32_cycles, gpu_box, oracle_params
+    print("fp32 stage-wise", opts, flush=True)
+    s = I.to_float32_exact(I.orszag_tang(32))
+    box = gpu_box((32, 32, 32), precision="fp32", **opts)
+    box.set_state(s)
+    kw = {k: v for k, v in opts.items() if k != "integrator"}
+    p = oracle_params((32, 32, 32), integrator=opts.get("integrator", "rk2"), **kw)
+    worst = check_fp32_cycles(box, p, 5, integrator=opts.get("integrator", "rk2"))
+    box.close()
+    print("worst", worst)
