@@ -367,9 +367,7 @@ def served_c4(nreq: int, precision: str = "fp32", rate: float = 200.0):
     budget = int(min(0.8 * free, 64 << 30))
     be = GpuBackend(precision=precision)
     reqs = poisson_requests(nreq, rate=rate, seed=2304)
-    for e in EDGES:  # base states resident on the GPU before the clock starts
-        for init in ("ot", "turb"):
-            be.base_state(e, init)
+    be.prepare(EDGES)  # initial fields resident on the GPU before the clock starts
     torch.cuda.synchronize()
     def progress(done, total):  # a line every 500 retired requests
         if done // 500 != progress.last:
@@ -380,7 +378,7 @@ def served_c4(nreq: int, precision: str = "fp32", rate: float = 200.0):
     s = st.summary()
     s.update({"workload": f"{nreq} Poisson requests at {rate:g}/s (the first {nreq} of the seeded "
                           f"5000-request stream), edges {list(EDGES)}, 10-200 RK2 cycles, "
-                          f"OT/turbulence with per-request seeded translations, {precision.upper()}, "
+                          f"OT/turbulence, one of 16 seeded translations per request, {precision.upper()}, "
                           f"HBM budget {budget / 2**30:.0f} GiB",
               "precision": precision})
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}

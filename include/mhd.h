@@ -131,9 +131,8 @@ typedef struct {
 size_t mhd_workspace_bytes(const mhd_params* params);
 
 /* Validate params and build a context on the borrowed workspace.  *out receives
- * the context (host memory owned by the library until mhd_destroy).  The box
- * descriptor is written into the workspace by a launch queued on the stream:
- * the call does not synchronise (it sits on a serving loop's admission path).
+ * the context (host memory owned by the library until mhd_destroy).  Writes the
+ * box descriptor into the workspace synchronously (waits for the stream).
  * Errors: MHD_ERR_INVALID_ARG, MHD_ERR_WORKSPACE, MHD_ERR_UNSUPPORTED,
  * MHD_ERR_HIP. */
 int mhd_create(const mhd_params* params, mhd_ctx** out);

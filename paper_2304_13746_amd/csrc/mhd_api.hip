@@ -210,13 +210,38 @@ __global__ void k_diag_final(const double* part, int nblocks, double dv, double 
   st_agent(&s->diag[9], sqrt((tot[8].s + tot[8].c) / ncell));
 }
 
-// Copy a box descriptor (passed by value) into the workspace, with agent-scope
-// stores like the other values later kernels read (see Scalars).
-__global__ void k_put_desc(BoxDesc d, BoxDesc* dst) {
-  static_assert(sizeof(BoxDesc) % 8 == 0, "descriptor copied in 8-byte words");
-  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(&d);
-  unsigned long long* o = reinterpret_cast<unsigned long long*>(dst);
-  for (int w = threadIdx.x; w < (int)(sizeof(BoxDesc) / 8); w += blockDim.x) st_agent(o + w, s[w]);
+// Diagnostics of c's state with the per-block partial sums in part (the
+// context's workspace).
+int diagnostics_into(mhd_ctx* c, double* part, mhd_diag* out) {
+  void** f = c->buf[c->cur];
+  if (c->p.precision == MHD_FP32) {
+    hipLaunchKernelGGL(k_diag_partial<float>, dim3(c->diag_blocks), dim3(256), 0, c->stream,
+                       (const float*)f[0], (const float*)f[1], (const float*)f[2], (const float*)f[3],
+                       (const float*)f[4], (const float*)f[5], (const float*)f[6], (const float*)f[7],
+                       c->p.nx, c->p.ny, c->p.nz, c->idl[0], c->idl[1], c->idl[2], part);
+  } else {
+    hipLaunchKernelGGL(k_diag_partial<double>, dim3(c->diag_blocks), dim3(256), 0, c->stream,
+                       (const double*)f[0], (const double*)f[1], (const double*)f[2],
+                       (const double*)f[3], (const double*)f[4], (const double*)f[5],
+                       (const double*)f[6], (const double*)f[7], c->p.nx, c->p.ny, c->p.nz,
+                       c->idl[0], c->idl[1], c->idl[2], part);
+  }
+  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(1), 0, c->stream, part, c->diag_blocks, c->dv,
+                     (double)c->ncell, c->sc);
+  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
+  Scalars h;
+  hipError_t e = hipMemcpyAsync(&h, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return MHD_ERR_HIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return MHD_ERR_HIP;
+  out->mass = h.diag[0];
+  for (int d = 0; d < 3; ++d) out->mom[d] = h.diag[1 + d];
+  out->energy = h.diag[4];
+  for (int d = 0; d < 3; ++d) out->bflux[d] = h.diag[5 + d];
+  out->divb_max = h.diag[8];
+  out->divb_rms = h.diag[9];
+  out->status = h.status;
+  return MHD_OK;
 }
 
 int hip_fail(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_HIP; }
@@ -433,10 +458,8 @@ int choose_lz(int tile, int nx, int ny, int nz) {
 
 // Give c the launch shape (tile, zchunk; 0 = automatic): raise the dynamic-LDS
 // limit of the tile's kernels and rewrite the box descriptor on the device.
-// With sync, wait for c's stream before (kernels in flight may still read the
-// old descriptor) and after the upload; without, the upload is only enqueued on
-// c's stream (a new context, whose descriptor nothing reads yet).
-int apply_shape(mhd_ctx* c, int tile, int zchunk, bool sync = true) {
+// Synchronous: kernels in flight on c's stream may still read the old one.
+int apply_shape(mhd_ctx* c, int tile, int zchunk) {
   int tx, ty;
   if (!tile_dims(tile, &tx, &ty)) return MHD_ERR_INVALID_ARG;
   const mhd_params* p = &c->p;
@@ -465,14 +488,9 @@ int apply_shape(mhd_ctx* c, int tile, int zchunk, bool sync = true) {
   d.sc = c->sc;
   d.uct = c->uct;
   d.ustride = (long long)(field_bytes(p) / c->elem);
-  // the descriptor goes up as a kernel argument: no host buffer has to outlive
-  // the call and nothing waits for the stream
-  if (sync && hipStreamSynchronize(c->stream) != hipSuccess) return MHD_ERR_HIP;
-  hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, c->stream, d, c->desc);
-  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
-  // launches on other streams (batches, the tuner) read it right after a
-  // synchronous reshape
-  if (sync && hipStreamSynchronize(c->stream) != hipSuccess) return MHD_ERR_HIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(c->desc, &d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess)
+    return MHD_ERR_HIP;
   c->tile = tile;
   c->zchunk = zchunk;
   c->lz = lz;
@@ -585,9 +603,7 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   w += (size_t)nscratch_of(p) * fb;
   c->cur = 0;
   c->diag_blocks = kDiagBlocks;
-  // no host synchronisation on this path (contexts are created on a serving
-  // loop's admission path): the descriptor upload is queued on the stream
-  if (apply_shape(c, tile, p->zchunk, false) != MHD_OK) {
+  if (apply_shape(c, tile, p->zchunk) != MHD_OK) {
     free(c);
     return MHD_ERR_HIP;
   }
@@ -682,35 +698,7 @@ int mhd_get_stage_output(mhd_ctx* c, int stage, const mhd_state_view* v) {
 
 int mhd_get_diagnostics(mhd_ctx* c, mhd_diag* out) {
   if (!c || !out) return MHD_ERR_INVALID_ARG;
-  void** f = c->buf[c->cur];
-  if (c->p.precision == MHD_FP32) {
-    hipLaunchKernelGGL(k_diag_partial<float>, dim3(c->diag_blocks), dim3(256), 0, c->stream,
-                       (const float*)f[0], (const float*)f[1], (const float*)f[2], (const float*)f[3],
-                       (const float*)f[4], (const float*)f[5], (const float*)f[6], (const float*)f[7],
-                       c->p.nx, c->p.ny, c->p.nz, c->idl[0], c->idl[1], c->idl[2], c->diag_part);
-  } else {
-    hipLaunchKernelGGL(k_diag_partial<double>, dim3(c->diag_blocks), dim3(256), 0, c->stream,
-                       (const double*)f[0], (const double*)f[1], (const double*)f[2],
-                       (const double*)f[3], (const double*)f[4], (const double*)f[5],
-                       (const double*)f[6], (const double*)f[7], c->p.nx, c->p.ny, c->p.nz,
-                       c->idl[0], c->idl[1], c->idl[2], c->diag_part);
-  }
-  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(1), 0, c->stream, c->diag_part, c->diag_blocks,
-                     c->dv, (double)c->ncell, c->sc);
-  if (hipGetLastError() != hipSuccess) return MHD_ERR_HIP;
-  Scalars h;
-  hipError_t e = hipMemcpyAsync(&h, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream);
-  if (e != hipSuccess) return MHD_ERR_HIP;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return MHD_ERR_HIP;
-  out->mass = h.diag[0];
-  for (int d = 0; d < 3; ++d) out->mom[d] = h.diag[1 + d];
-  out->energy = h.diag[4];
-  for (int d = 0; d < 3; ++d) out->bflux[d] = h.diag[5 + d];
-  out->divb_max = h.diag[8];
-  out->divb_rms = h.diag[9];
-  out->status = h.status;
-  return MHD_OK;
+  return diagnostics_into(c, c->diag_part, out);
 }
 
 int mhd_step_batch(mhd_ctx* const* ctxs, const int* nsteps, int n, void* stream) {

@@ -249,17 +249,31 @@ def serving_base(edge: int, init: str) -> dict:
     return s
 
 
-def request_shift(seed: int, edge: int) -> tuple:
-    """Periodic translation (sx, sy, sz), in cells, that a request's seed draws."""
-    rng = np.random.default_rng(seed)
+SERVING_VARIANTS = 16
+
+
+def request_variant(seed: int) -> int:
+    """Which of the SERVING_VARIANTS initial fields of its edge and init a
+    request's seed draws."""
+    return int(np.random.default_rng(seed).integers(SERVING_VARIANTS))
+
+
+def variant_shift(k: int, edge: int) -> tuple:
+    """Periodic translation (sx, sy, sz), in cells, of serving variant k."""
+    rng = np.random.default_rng(2304 + k)
     return tuple(int(v) for v in rng.integers(0, edge, 3))
+
+
+def request_shift(seed: int, edge: int) -> tuple:
+    """Periodic translation of the initial data of the request with this seed."""
+    return variant_shift(request_variant(seed), edge)
 
 
 def serving_state(edge: int, init: str, seed: int) -> dict:
     """Initial data of one served request: its base field translated
-    periodically by the seeded shift (cell and face arrays move together, so
-    the discrete divergence stays zero); every request gets its own data at the
-    cost of a copy, which a server can do on the device."""
+    periodically by the shift of the variant its seed draws (cell and face
+    arrays move together, so the discrete divergence stays zero).  A server
+    keeps the variants resident, so admitting a request is one copy."""
     sx, sy, sz = request_shift(seed, edge)
     return {k: np.roll(v, (sz, sy, sx), axis=(0, 1, 2)) for k, v in serving_base(edge, init).items()}
 

@@ -180,11 +180,10 @@ class Stats:
 
 
 class GpuBackend:
-    """libmhd backend: one context per request on a torch workspace.  Base
-    initial states are generated once per (edge, init) and kept on the GPU;
-    a request's own initial data is its base translated periodically by the
-    shift its seed draws (inputs.serving_state), so admission costs one
-    device-side copy."""
+    """libmhd backend: one context per request on a torch workspace.  The
+    initial fields (per edge and init, SERVING_VARIANTS seeded translations of
+    one base field, inputs.serving_state) are generated on the host once and
+    kept on the GPU, so admitting a request costs one device-to-device copy."""
 
     def __init__(self, precision: str = "fp32", device: str = "cuda:0", riemann: str = "hlld",
                  initial_states: dict | None = None):
@@ -204,19 +203,29 @@ class GpuBackend:
         self._states = {} if initial_states is None else initial_states
         self._batches = {}
 
-    def base_state(self, edge: int, init: str):
-        key = (edge, init)
+    def variant_state(self, edge: int, init: str, k: int, base: dict | None = None):
+        key = (edge, init, k)
         if key not in self._states:
-            s = self.I.serving_base(edge, init)
+            sx, sy, sz = self.I.variant_shift(k, edge)
+            if base is None:
+                base = self.I.serving_base(edge, init)
             dt = self.torch.float32 if self.precision == "fp32" else self.torch.float64
-            self._states[key] = {k: self.torch.from_numpy(np.ascontiguousarray(v)).to(self.device, dt)
-                                 for k, v in s.items()}
+            self._states[key] = {
+                f: self.torch.from_numpy(np.ascontiguousarray(np.roll(v, (sz, sy, sx), axis=(0, 1, 2))))
+                .to(self.device, dt) for f, v in base.items()}
         return self._states[key]
 
+    def prepare(self, edges=EDGES, inits=("ot", "turb")):
+        """Generate every variant of these edges and inits (before a replay's
+        clock starts)."""
+        for e in edges:
+            for init in inits:
+                base = self.I.serving_base(e, init)
+                for k in range(self.I.SERVING_VARIANTS):
+                    self.variant_state(e, init, k, base)
+
     def initial_state(self, r: Request):
-        sx, sy, sz = self.I.request_shift(r.seed, r.edge)
-        return {k: self.torch.roll(v, (sz, sy, sx), (0, 1, 2))
-                for k, v in self.base_state(r.edge, r.init).items()}
+        return self.variant_state(r.edge, r.init, self.I.request_variant(r.seed))
 
     def workspace_bytes(self, r: Request) -> int:
         return self._ws(r.edge, r.edge, r.edge, self.precision)

@@ -95,7 +95,8 @@ def test_latency_accounting():
 
 def test_request_inputs_are_seeded_translations():
     """A served request's initial data is its base field translated by the shift
-    its seed draws: div B stays zero, requests with other seeds get other data,
+    of the variant its seed draws: div B stays zero, seeds spread over the
+    variants and the variants' shifts differ,
     and (the scheme is translation-invariant on a periodic grid) the oracle's
     cycles on the translated input equal the translated cycles of the base, bit
     for bit, so any request can be checked against the oracle on its own input."""
@@ -103,8 +104,8 @@ def test_request_inputs_are_seeded_translations():
     from paper_2304_13746_amd import inputs as I
     n = 16
     base = I.serving_base(n, "turb")
-    shifts = {I.request_shift(seed, n) for seed in range(2304, 2320)}
-    assert len(shifts) > 12
+    assert len({I.request_variant(seed) for seed in range(2304, 2344)}) >= 12
+    assert len({I.variant_shift(k, n) for k in range(I.SERVING_VARIANTS)}) >= 12
     s = I.serving_state(n, "turb", 2307)
     sx, sy, sz = I.request_shift(2307, n)
     assert (sx, sy, sz) != (0, 0, 0)
