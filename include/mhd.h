@@ -167,6 +167,17 @@ int mhd_get_stage_output(mhd_ctx* ctx, int stage, const mhd_state_view* dst);
  * state.  Synchronises the stream. */
 int mhd_get_diagnostics(mhd_ctx* ctx, mhd_diag* out);
 
+/* mhd_get_diagnostics for callers that cannot allocate device memory or must not
+ * touch the context's workspace beyond its state (code under graph capture
+ * elsewhere on the device, serving loops with a fixed memory plan): the same
+ * kernels and the same bits, with the per-block partial sums in a static device
+ * array of the library (80 KiB per GPU, held until the process ends) instead of
+ * the workspace.  Allocates nothing.  Calls on one GPU share that array, so
+ * calls that overlap in time on one GPU (other threads, other streams) race;
+ * serialise them.  MHD_ERR_INVALID_ARG for a null argument, MHD_ERR_HIP if the
+ * array's device address cannot be resolved.  Synchronises the stream. */
+int mhd_get_diagnostics_noalloc(mhd_ctx* ctx, mhd_diag* out);
+
 /* Advance n (0 <= n <= 4096) contexts by nsteps[i] >= 0 cycles each on one
  * stream (NULL: the stream of ctxs[0]).  Each stage of a cycle is one launch
  * whose blocks cover the tiles of every box still stepping (up to 64 boxes per

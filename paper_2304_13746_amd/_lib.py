@@ -28,7 +28,8 @@ MHD_RK2, MHD_EULER, MHD_RK3 = 0, 1, 2
 TILE_16x16, TILE_24x8, TILE_18x11 = 1, 2, 3
 
 EXPORTED = ("mhd_workspace_bytes", "mhd_create", "mhd_set_state", "mhd_step", "mhd_get_state",
-            "mhd_get_stage_output", "mhd_get_diagnostics", "mhd_step_batch", "mhd_set_launch",
+            "mhd_get_stage_output", "mhd_get_diagnostics", "mhd_get_diagnostics_noalloc",
+            "mhd_step_batch", "mhd_set_launch",
             "mhd_get_launch", "mhd_tune", "mhd_destroy", "mhd_status_string")
 
 
@@ -85,6 +86,7 @@ def lib():
         L.mhd_get_state.argtypes = [C.c_void_p, P(StateView), P(C.c_double), P(C.c_double)]
         L.mhd_get_stage_output.argtypes = [C.c_void_p, C.c_int, P(StateView)]
         L.mhd_get_diagnostics.argtypes = [C.c_void_p, P(Diag)]
+        L.mhd_get_diagnostics_noalloc.argtypes = [C.c_void_p, P(Diag)]
         L.mhd_step_batch.argtypes = [P(C.c_void_p), P(C.c_int), C.c_int, C.c_void_p]
         L.mhd_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.mhd_get_launch.argtypes = [C.c_void_p, P(C.c_int), P(C.c_int)]

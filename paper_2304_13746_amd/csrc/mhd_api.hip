@@ -5,6 +5,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/mhd.h"
 #include "mhd_internal.h"
 
@@ -211,7 +213,7 @@ __global__ void k_diag_final(const double* part, int nblocks, double dv, double 
 }
 
 // Diagnostics of c's state with the per-block partial sums in part (the
-// context's workspace).
+// context's workspace, or the static scratch of the allocation-free variant).
 int diagnostics_into(mhd_ctx* c, double* part, mhd_diag* out) {
   void** f = c->buf[c->cur];
   if (c->p.precision == MHD_FP32) {
@@ -242,6 +244,32 @@ int diagnostics_into(mhd_ctx* c, double* part, mhd_diag* out) {
   out->divb_rms = h.diag[9];
   out->status = h.status;
   return MHD_OK;
+}
+
+// ---- the allocation-free diagnostics variant: its partial sums live in a
+// static device array, one copy per GPU held until the process ends (80 KiB).
+// In host code `scratch` only names the symbol; its device address, resolved
+// once per device with that device current, is what kernels receive.  Calls
+// that overlap on one GPU share the array and race.
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kDiagBlocks * kDiagVals];
+double* g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+double* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev && hipSetDevice(cur) != hipSuccess) return nullptr;
+    if (e != hipSuccess || !ptr) return nullptr;
+    g_scratch[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch[dev];
 }
 
 int hip_fail(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_ERR_HIP; }
@@ -699,6 +727,16 @@ int mhd_get_stage_output(mhd_ctx* c, int stage, const mhd_state_view* v) {
 int mhd_get_diagnostics(mhd_ctx* c, mhd_diag* out) {
   if (!c || !out) return MHD_ERR_INVALID_ARG;
   return diagnostics_into(c, c->diag_part, out);
+}
+
+int mhd_get_diagnostics_noalloc(mhd_ctx* c, mhd_diag* out) {
+  if (!c || !out) return MHD_ERR_INVALID_ARG;
+  // one partial row per reduction block: the block count is fixed, so every box
+  // fits (grid-stride loop); a larger count would not fit the static rows
+  if (c->diag_blocks > kDiagBlocks) return MHD_ERR_INVALID_ARG;
+  double* part = scratch_ptr(c->device);
+  if (!part) return MHD_ERR_HIP;
+  return diagnostics_into(c, part, out);
 }
 
 int mhd_step_batch(mhd_ctx* const* ctxs, const int* nsteps, int n, void* stream) {
