@@ -26,7 +26,7 @@ FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
 
 HLLD, HLL, HLLC = 0, 1, 2
 RK2, EULER, RK3 = 0, 1, 2
-EMF_EC, EMF_E0, EMF_ARITH, EMF_UCT_HLL = 0, 1, 2, 3
+EMF_EC, EMF_E0, EMF_ARITH, EMF_UCT_HLL, EMF_UCT_HLLD = 0, 1, 2, 3, 4
 PLM, LIMO3, PPM = 0, 1, 2
 OK, ERR_INVALID_ARG, ERR_NOMEM, ERR_NONPHYSICAL = 0, -1, -2, -4
 
@@ -92,6 +92,8 @@ def lib():
             fn.argtypes = [C.c_double] * 6
             fn.restype = C.c_double
         L.orc_riemann.argtypes = [C.c_int, C.c_double, C.c_int, dp, dp, dp, dp, dp]
+        L.orc_uct_hlld_coef.argtypes = [C.c_double, C.c_int, dp, dp, dp, dp]
+        L.orc_uct_hlld_coef.restype = None
         L.orc_phys_flux.argtypes = [C.c_double, dp, C.c_double, dp, dp]
         L.orc_corner_emf.argtypes = [C.c_double] * 12
         L.orc_corner_emf.restype = C.c_double
@@ -231,6 +233,18 @@ def ppm_faces(a) -> tuple:
     lo, hi = C.c_double(), C.c_double()
     lib().orc_ppm_faces(_dptr(arr), C.byref(lo), C.byref(hi))
     return lo.value, hi.value
+
+
+def uct_hlld_coef(gamma: float, wl: np.ndarray, wr: np.ndarray, bn: np.ndarray):
+    """UCT-HLLD coefficients (aL, aR, dL, dR) of n faces, shape (n, 4)."""
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    bn = np.ascontiguousarray(bn, dtype=np.float64)
+    n = bn.shape[0]
+    assert wl.shape == (n, 7) and wr.shape == (n, 7)
+    out = np.zeros((n, 4))
+    lib().orc_uct_hlld_coef(gamma, n, _dptr(wl), _dptr(wr), _dptr(bn), _dptr(out))
+    return out
 
 
 def fast_speed(gamma, rho, p, bn, bt1, bt2) -> float:

@@ -20,7 +20,9 @@
  *       the CFL condition (eq. cfl).
  *   S5  conservative update of (rho, m, E) by the flux divergence (eq. gal).
  *   S7  corner EMFs with the upwind-by-contact scheme E^c of Gardiner & Stone
- *       (2005), the default of Sec. 2.4, or its E^0 and arithmetic variants.
+ *       (2005), the default of Sec. 2.4, or its E^0 and arithmetic variants, or
+ *       the edge solves UCT-HLL and UCT-HLLD (Sec. 2.4, after Mignone & Del
+ *       Zanna 2021).
  *   S8  face-B update by the discrete Stokes theorem (constrained transport,
  *       eq. ind_short).
  *   Stages are combined as U_s = w_s U* + w0_s U_0 (Sec. 2.7, Tab. weights);
@@ -80,12 +82,14 @@ static int check_params(const orc_params* p) {
   if (p->integrator != ORC_RK2 && p->integrator != ORC_EULER && p->integrator != ORC_RK3)
     return ORC_ERR_INVALID_ARG;
   if (p->emf != ORC_EMF_EC && p->emf != ORC_EMF_E0 && p->emf != ORC_EMF_ARITH &&
-      p->emf != ORC_EMF_UCT_HLL)
+      p->emf != ORC_EMF_UCT_HLL && p->emf != ORC_EMF_UCT_HLLD)
     return ORC_ERR_INVALID_ARG;
   if (p->recon != ORC_PLM && p->recon != ORC_LIMO3 && p->recon != ORC_PPM)
     return ORC_ERR_INVALID_ARG;
   /* the edge solve needs a magnetic Riemann solver */
   if (p->emf == ORC_EMF_UCT_HLL && p->riemann == ORC_HLLC) return ORC_ERR_INVALID_ARG;
+  /* UCT-HLLD takes its coefficients from the HLLD solve of each face */
+  if (p->emf == ORC_EMF_UCT_HLLD && p->riemann != ORC_HLLD) return ORC_ERR_INVALID_ARG;
   return ORC_OK;
 }
 
@@ -478,6 +482,128 @@ static void hlld(double gamma, double igm1, const double* wl, const double* wr, 
   }
 }
 
+/* UCT-HLLD coefficients (Sec. 2.4 names the HLLD 2D Riemann solver of Mignone &
+ * Del Zanna 2021 without printing it).  Across one face, the HLLD flux of a
+ * tangential field component B_t is linear in the two sides' B_t and v_t: with
+ *   B*_a = chi_a B_a,  chi_a = (rho_a (S_a - u_a)^2 - B_n^2) / den_a,
+ *   v*_a = v_a - tv_a B_a,  tv_a = B_n (S_M - u_a) / den_a
+ * (chi = 1, tv = 0 in the degenerate case) and, across the rotational
+ * discontinuities,
+ *   B** = [sqL B*_R + sqR B*_L + sqL sqR sgn(B_n) (v*_R - v*_L)] / (sqL + sqR)
+ *       = betaL B_L + betaR B_R + g (v_R - v_L),
+ *   betaL = (sqR chi_L + sqL sqR sgn(B_n) tv_L) / (sqL + sqR),
+ *   betaR = (sqL chi_R - sqL sqR sgn(B_n) tv_R) / (sqL + sqR),
+ *   g = sqL sqR sgn(B_n) / (sqL + sqR),
+ * the flux in each region of the fan, F = F_a + S_a (B*_a - B_a) and
+ * F** = F* + S*_a (B** - B*_a), can be written as
+ *   aL u_L B_L + aR u_R B_R - (dR B_R - dL B_L) - B_n (aL v_L + aR v_R)
+ * with aL + aR = 1.  Matching the coefficients of B_L, B_R, v_L and v_R:
+ *   L:   aL = 1, aR = 0, dL = dR = 0;      R: aL = 0, aR = 1, dL = dR = 0;
+ *   *L:  aL = 1, aR = 0, dL = S_L (chi_L - 1), dR = 0;
+ *   *R:  aL = 0, aR = 1, dL = 0, dR = -S_R (chi_R - 1);
+ *   **L: aR = -S*_L sqL sqR / ((sqL + sqR) |B_n|), aL = 1 - aR,
+ *        dL = u_L + S_L (chi_L - 1) + S*_L (betaL - chi_L) - aL u_L,
+ *        dR = aR u_R - S*_L betaR;
+ *   **R: aL = S*_R sqL sqR / ((sqL + sqR) |B_n|), aR = 1 - aL,
+ *        dL = S*_R betaL - aL u_L,
+ *        dR = aR u_R - (u_R + S_R (chi_R - 1) + S*_R (betaR - chi_R)).
+ * (The double-star regions need B_n != 0, where S*_L < 0 <= S_M bounds
+ * |S*_L| by |B_n| / sqL, so the quotients stay bounded.)  The region is chosen
+ * by the same tests as in hlld().  The edge solve combines these coefficients
+ * of the faces it crosses (see emfs_uct). */
+static void hlld_uct_coef(double gamma, double igm1, const double* wl, const double* wr,
+                          double bn, double* al, double* ar, double* dl_, double* dr_) {
+  const double eps = 1e-12;
+  double ul[7], fl[7], ur[7], fr[7], ptl, ptr, sl, sr, cmax;
+  phys(igm1, wl, bn, ul, fl, &ptl);
+  phys(igm1, wr, bn, ur, fr, &ptr);
+  outer_speeds(gamma, wl, wr, bn, &sl, &sr, &cmax);
+  *dl_ = 0.0;
+  *dr_ = 0.0;
+  if (sl >= 0.0) {
+    *al = 1.0;
+    *ar = 0.0;
+    return;
+  }
+  if (sr <= 0.0) {
+    *al = 0.0;
+    *ar = 1.0;
+    return;
+  }
+  /* the contact speed as in hlld() */
+  double dl = (sl - wl[1]) * wl[0];
+  double dr = (sr - wr[1]) * wr[0];
+  double iden = 1.0 / (dr - dl);
+  double sm = (((dr * wr[1] - dl * wl[1]) - ptr) + ptl) * iden;
+  /* per side: star density, chi and tv (the same expressions as hlld_star) */
+  const double* ws[2] = {wl, wr};
+  const double sa[2] = {sl, sr};
+  double rhos[2], chi[2], tv[2];
+  for (int a = 0; a < 2; ++a) {
+    double sua = sa[a] - ws[a][1];
+    double da = sua * ws[a][0];
+    double sam = sa[a] - sm;
+    double isam = 1.0 / sam;
+    rhos[a] = da * isam;
+    double t = da * sam;
+    double bn2 = bn * bn;
+    double den = t - bn2;
+    if (fabs(den) <= eps * (fabs(t) + bn2)) {
+      chi[a] = 1.0;
+      tv[a] = 0.0;
+    } else {
+      double idn = 1.0 / den;
+      tv[a] = (bn * (sm - ws[a][1])) * idn;
+      chi[a] = (da * sua - bn2) * idn;
+    }
+  }
+  double sql = sqrt(rhos[0]), sqr = sqrt(rhos[1]);
+  double abn = fabs(bn);
+  double ssl = sm - abn / sql;
+  double ssr = sm + abn / sqr;
+  if (ssl >= 0.0) { /* *L */
+    *al = 1.0;
+    *ar = 0.0;
+    *dl_ = sl * (chi[0] - 1.0);
+    return;
+  }
+  if (!(sm >= 0.0) && !(ssr >= 0.0)) { /* *R */
+    *al = 0.0;
+    *ar = 1.0;
+    *dr_ = -(sr * (chi[1] - 1.0));
+    return;
+  }
+  double sgn = bn > 0.0 ? 1.0 : (bn < 0.0 ? -1.0 : 0.0);
+  double isq = 1.0 / (sql + sqr);
+  double pq = sql * sqr;
+  double betal = (sqr * chi[0] + pq * (sgn * tv[0])) * isq;
+  double betar = (sql * chi[1] - pq * (sgn * tv[1])) * isq;
+  double ul0 = wl[1], ur0 = wr[1];
+  if (sm >= 0.0) { /* **L */
+    double a_r = -(ssl * (pq * isq)) / abn;
+    double a_l = 1.0 - a_r;
+    *al = a_l;
+    *ar = a_r;
+    *dl_ = ((ul0 + sl * (chi[0] - 1.0)) + ssl * (betal - chi[0])) - a_l * ul0;
+    *dr_ = a_r * ur0 - ssl * betar;
+  } else { /* **R */
+    double a_l = (ssr * (pq * isq)) / abn;
+    double a_r = 1.0 - a_l;
+    *al = a_l;
+    *ar = a_r;
+    *dl_ = ssr * betal - a_l * ul0;
+    *dr_ = a_r * ur0 - ((ur0 + sr * (chi[1] - 1.0)) + ssr * (betar - chi[1]));
+  }
+}
+
+void orc_uct_hlld_coef(double gamma, int n, const double* wl, const double* wr, const double* bn,
+                       double* coef) {
+  double igm1 = 1.0 / (gamma - 1.0);
+  for (int i = 0; i < n; ++i)
+    hlld_uct_coef(gamma, igm1, wl + 7 * i, wr + 7 * i, bn[i], coef + 4 * i, coef + 4 * i + 1,
+                  coef + 4 * i + 2, coef + 4 * i + 3);
+}
+
 static void riemann(int solver, double gamma, double igm1, const double* wl, const double* wr,
                     double bn, double* f, double* cmax) {
   if (solver == ORC_HLL)
@@ -533,7 +659,9 @@ double orc_corner_emf_scheme(int scheme, double a1, double a2, double b1, double
 /* --------------------------------------------------------------- stage */
 
 enum { W_RHO, W_VX, W_VY, W_VZ, W_BX, W_BY, W_BZ, W_P, NW };
-enum { F_RHO, F_MX, F_MY, F_MZ, F_EN, F_B1, F_B2, F_CMAX, F_AP, F_AM, F_VT1, F_VT2, NF };
+/* edge-solve face data: UCT-HLL keeps alpha+ in F_AP and alpha- in F_AM; UCT-HLLD
+ * keeps aL, aR there and dL, dR in F_DL, F_DR */
+enum { F_RHO, F_MX, F_MY, F_MZ, F_EN, F_B1, F_B2, F_CMAX, F_AP, F_AM, F_VT1, F_VT2, F_DL, F_DR, NF };
 
 typedef struct {
   double* w[NW];     /* primitives per cell */
@@ -645,6 +773,17 @@ static void faces(const grid_t* g, const orc_state* s, work_t* w, int d) {
           w->f[d][F_AM][o] = am;
           w->f[d][F_VT1][o] = (ap * wl[2] + am * wr[2]) / (ap + am);
           w->f[d][F_VT2][o] = (ap * wl[3] + am * wr[3]) / (ap + am);
+        } else if (g->emf == ORC_EMF_UCT_HLLD) {
+          /* the HLLD coefficients of this face and the transverse velocities
+           * they weight (the velocity the HLLD flux of B_t carries) */
+          double a_l, a_r, d_l, d_r;
+          hlld_uct_coef(g->gamma, g->igm1, wl, wr, bnarr[o], &a_l, &a_r, &d_l, &d_r);
+          w->f[d][F_AP][o] = a_l;
+          w->f[d][F_AM][o] = a_r;
+          w->f[d][F_DL][o] = d_l;
+          w->f[d][F_DR][o] = d_r;
+          w->f[d][F_VT1][o] = a_l * wl[2] + a_r * wr[2];
+          w->f[d][F_VT2][o] = a_l * wl[3] + a_r * wr[3];
         }
         w->f[d][F_RHO][o] = fl[0];
         w->f[d][mom_of[d][0]][o] = fl[1];
@@ -709,7 +848,7 @@ static void emfs(const grid_t* g, work_t* w) {
   }
 }
 
-/* UCT-HLL corner EMFs (Sec. 2.4, the class that solves a 2D Riemann problem at
+/* UCT-HLL and UCT-HLLD corner EMFs (Sec. 2.4, the class that solves a 2D Riemann problem at
  * each edge, Londrillo & Del Zanna 2004, in the form of Mignone & Del Zanna
  * 2021).  For the edge along e with the cyclic plane (P, Q), E_e = v_Q B_P -
  * v_P B_Q is split into two 1D HLL fluxes across the edge:
@@ -721,12 +860,39 @@ static void emfs(const grid_t* g, work_t* w) {
  *   F = (a+ vL bL + a- vR bR - a+ a- (bR - bL)) / (a+ + a-),
  *   E_e = F_Q - F_P.
  * On data that vary along one axis only this is the HLL face flux of the
- * tangential field, as for the face-flux schemes. */
+ * tangential field, as for the face-flux schemes.  UCT-HLLD takes the same
+ * two 1D fluxes with the HLLD coefficients of the faces it crosses (averaged
+ * over the two faces that share the edge, see hlld_uct_coef and uct_part_d)
+ * and the transverse velocities averaged with those coefficients; it reduces
+ * to the HLLD face flux of the tangential field. */
 static double uct_part(double ap, double am, double vl, double bl, double vr, double br) {
   return ((ap * (vl * bl) + am * (vr * br)) - (ap * am) * (br - bl)) / (ap + am);
 }
 
 static double dmax(double a, double b) { return a > b ? a : b; }
+
+/* UCT-HLLD: the 1D flux of v B across an edge with the HLLD coefficients of the
+ * two faces it crosses, averaged (c[0..3] = aL, aR, dL, dR of one face, e[0..3]
+ * of the other):  a_L vL bL + a_R vR bR - (d_R bR - d_L bL). */
+static double uct_part_d(const double* c, const double* e, double vl, double bl, double vr,
+                         double br) {
+  double a_l = 0.5 * (c[0] + e[0]), a_r = 0.5 * (c[1] + e[1]);
+  double d_l = 0.5 * (c[2] + e[2]), d_r = 0.5 * (c[3] + e[3]);
+  return (a_l * (vl * bl) + a_r * (vr * br)) - (d_r * br - d_l * bl);
+}
+
+/* the edge flux of either scheme from the face data of faces f1, f2 of one
+ * direction's arrays */
+static double edge_part(int emf, double* const* fd, long f1, long f2, double vl, double bl,
+                        double vr, double br) {
+  if (emf == ORC_EMF_UCT_HLLD) {
+    double c[4] = {fd[F_AP][f1], fd[F_AM][f1], fd[F_DL][f1], fd[F_DR][f1]};
+    double e[4] = {fd[F_AP][f2], fd[F_AM][f2], fd[F_DL][f2], fd[F_DR][f2]};
+    return uct_part_d(c, e, vl, bl, vr, br);
+  }
+  return uct_part(dmax(fd[F_AP][f1], fd[F_AP][f2]), dmax(fd[F_AM][f1], fd[F_AM][f2]), vl, bl, vr,
+                  br);
+}
 
 /* the value at the edge from the low side (upper face of the cell below) and
  * from the high side (lower face of the cell above), with the cell
@@ -767,8 +933,7 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           to_edge(r, b, &bl, &br);
           to_edge(r, v, &vl, &vr);
           long cjm = at(g, i, jm, k);
-          double fp = uct_part(dmax(fx[F_AP][cjm], fx[F_AP][c]), dmax(fx[F_AM][cjm], fx[F_AM][c]),
-                               vl, bl, vr, br);
+          double fp = edge_part(g->emf, fx, cjm, c, vl, bl, vr, br);
           for (int q = 0; q < 6; ++q) {  /* x-faces (i-1/2, j-3 .. j+2) */
             long f = at(g, i, wrap(j - 3 + q, g->ny), k);
             b[q] = s->bx[f];
@@ -777,8 +942,7 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           to_edge(r, b, &bl, &br);
           to_edge(r, v, &vl, &vr);
           long cim = at(g, im, j, k);
-          double fq = uct_part(dmax(fy[F_AP][cim], fy[F_AP][c]), dmax(fy[F_AM][cim], fy[F_AM][c]),
-                               vl, bl, vr, br);
+          double fq = edge_part(g->emf, fy, cim, c, vl, bl, vr, br);
           w->ed[2][c] = fq - fp;
         }
         /* E_x at (i, j-1/2, k-1/2): P = y, Q = z */
@@ -791,8 +955,7 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           to_edge(r, b, &bl, &br);
           to_edge(r, v, &vl, &vr);
           long ckm = at(g, i, j, km);
-          double fp = uct_part(dmax(fy[F_AP][ckm], fy[F_AP][c]), dmax(fy[F_AM][ckm], fy[F_AM][c]),
-                               vl, bl, vr, br);
+          double fp = edge_part(g->emf, fy, ckm, c, vl, bl, vr, br);
           for (int q = 0; q < 6; ++q) {  /* y-faces (i, j-1/2, k-3 .. k+2) */
             long f = at(g, i, j, wrap(k - 3 + q, g->nz));
             b[q] = s->by[f];
@@ -801,8 +964,7 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           to_edge(r, b, &bl, &br);
           to_edge(r, v, &vl, &vr);
           long cjm = at(g, i, jm, k);
-          double fq = uct_part(dmax(fz[F_AP][cjm], fz[F_AP][c]), dmax(fz[F_AM][cjm], fz[F_AM][c]),
-                               vl, bl, vr, br);
+          double fq = edge_part(g->emf, fz, cjm, c, vl, bl, vr, br);
           w->ed[0][c] = fq - fp;
         }
         /* E_y at (i-1/2, j, k-1/2): P = z, Q = x */
@@ -815,8 +977,7 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           to_edge(r, b, &bl, &br);
           to_edge(r, v, &vl, &vr);
           long cim = at(g, im, j, k);
-          double fp = uct_part(dmax(fz[F_AP][cim], fz[F_AP][c]), dmax(fz[F_AM][cim], fz[F_AM][c]),
-                               vl, bl, vr, br);
+          double fp = edge_part(g->emf, fz, cim, c, vl, bl, vr, br);
           for (int q = 0; q < 6; ++q) {  /* z-faces (i-3 .. i+2, j, k-1/2) */
             long f = at(g, wrap(i - 3 + q, g->nx), j, k);
             b[q] = s->bz[f];
@@ -825,8 +986,7 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
           to_edge(r, b, &bl, &br);
           to_edge(r, v, &vl, &vr);
           long ckm = at(g, i, j, km);
-          double fq = uct_part(dmax(fx[F_AP][ckm], fx[F_AP][c]), dmax(fx[F_AM][ckm], fx[F_AM][c]),
-                               vl, bl, vr, br);
+          double fq = edge_part(g->emf, fx, ckm, c, vl, bl, vr, br);
           w->ed[1][c] = fq - fp;
         }
       }
@@ -847,7 +1007,7 @@ static int stage(const grid_t* g, const orc_state* src, const orc_state* base, d
                  const orc_vpot* asrc, const orc_vpot* abase, orc_vpot* adst) {
   int bad = prim_all(g, src, w);
   for (int d = 0; d < 3; ++d) faces(g, src, w, d);
-  if (g->emf == ORC_EMF_UCT_HLL)
+  if (g->emf == ORC_EMF_UCT_HLL || g->emf == ORC_EMF_UCT_HLLD)
     emfs_uct(g, src, w);
   else
     emfs(g, w);

@@ -24,7 +24,7 @@ enum { ORC_RK2 = 0, ORC_EULER = 1, ORC_RK3 = 2 };
 /* corner-EMF schemes of Sec. 2.4: E^c (default), E^0, arithmetic average (all
  * from the face fluxes), and UCT-HLL, a 2D HLL Riemann solve at each edge
  * (MHD solvers only) */
-enum { ORC_EMF_EC = 0, ORC_EMF_E0 = 1, ORC_EMF_ARITH = 2, ORC_EMF_UCT_HLL = 3 };
+enum { ORC_EMF_EC = 0, ORC_EMF_E0 = 1, ORC_EMF_ARITH = 2, ORC_EMF_UCT_HLL = 3, ORC_EMF_UCT_HLLD = 4 };
 /* reconstructions of Sec. 2.3: van Leer PLM (default), LimO3, PPM */
 enum { ORC_PLM = 0, ORC_LIMO3 = 1, ORC_PPM = 2 };
 
@@ -42,7 +42,8 @@ typedef struct {
   double cfl;          /* sigma_CFL of eq. (cfl), in (0, 1) */
   int riemann;         /* ORC_HLLD, ORC_HLL or ORC_HLLC */
   int integrator;      /* ORC_RK2, ORC_EULER or ORC_RK3 (Tab. weights) */
-  int emf;             /* ORC_EMF_EC, ORC_EMF_E0, ORC_EMF_ARITH or ORC_EMF_UCT_HLL */
+  int emf;             /* ORC_EMF_EC, ORC_EMF_E0, ORC_EMF_ARITH, ORC_EMF_UCT_HLL or
+                          ORC_EMF_UCT_HLLD (the latter with ORC_HLLD only) */
   int recon;           /* ORC_PLM, ORC_LIMO3 or ORC_PPM */
 } orc_params;
 
@@ -68,6 +69,14 @@ typedef struct {
  * stage weights like U) and re-derives the face field from it. */
 int orc_step_vp(const orc_params* p, orc_state* s, orc_vpot* a, double* t, double* dt_next,
                 int nsteps, double t_stop);
+
+/* UCT-HLLD coefficients of n faces (states wl, wr as for orc_riemann): the HLLD
+ * flux of either tangential field component written as
+ *   aL u_L B_L + aR u_R B_R - (dR B_R - dL B_L) - B_n (aL v_L + aR v_R)
+ * (u the normal velocity, B and v the tangential field and velocity of each
+ * side).  coef receives (aL, aR, dL, dR) per face. */
+void orc_uct_hlld_coef(double gamma, int n, const double* wl, const double* wr, const double* bn,
+                       double* coef);
 
 /* Mass flux F_rho of the Riemann solve (S3) on every face of the state: fx[c] on
  * the x-face at (i-1/2, j, k) of cell c, fy and fz likewise (arrays of n cells). */
