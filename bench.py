@@ -467,8 +467,8 @@ def main():
     if not args.no_next:
         # widened scheme options on the same input: the third-order Runge-Kutta
         # cycle (three stage launches per cycle), LimO3 and PPM reconstructions
-        # with RK3, and the E^0 / arithmetic / UCT-HLL corner EMFs (RK2; UCT-HLL
-        # adds two light launches per stage)
+        # with RK3, and the E^0 / arithmetic / UCT-HLL / UCT-HLLD corner EMFs
+        # (RK2; the edge solves add two light launches per stage)
         nxt = {}
         k = min(args.steps, 20)
         for name, integ, emf, recon, nst in (("rk3", "rk3", "ec", "plm", 3),
@@ -476,7 +476,8 @@ def main():
                                              ("ppm_rk3", "rk3", "ec", "ppm", 3),
                                              ("emf_e0", "rk2", "e0", "plm", 2),
                                              ("emf_arith", "rk2", "arith", "plm", 2),
-                                             ("emf_uct_hll", "rk2", "uct_hll", "plm", 2)):
+                                             ("emf_uct_hll", "rk2", "uct_hll", "plm", 2),
+                                             ("emf_uct_hlld", "rk2", "uct_hlld", "plm", 2)):
             for prec in precs:
                 r = run_gpu(state, prec, k, 1, args.tile, args.zchunk, integ, emf, recon)
                 ms_step = r["ms_total"] / k

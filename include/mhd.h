@@ -65,8 +65,19 @@ typedef enum { MHD_HLLD = 0, MHD_HLL = 1, MHD_HLLC = 2 } mhd_riemann;
  * UCT-HLL is built for HLLD/HLL with every reconstruction and either CT form
  * (else MHD_ERR_UNSUPPORTED); it runs two extra
  * one-thread-per-cell launches per stage and needs 15 more arrays of one field
- * in the workspace (mhd_workspace_bytes accounts for them). */
-typedef enum { MHD_EMF_EC = 0, MHD_EMF_E0 = 1, MHD_EMF_ARITH = 2, MHD_EMF_UCT_HLL = 3 } mhd_emf;
+ * in the workspace (mhd_workspace_bytes accounts for them).  UCT-HLLD (the HLLD
+ * 2D solver Sec. 2.4 lists, after Mignone & Del Zanna 2021) is the same edge
+ * solve with coefficients from each face's HLLD solve: the HLLD flux of B_t
+ * written as aL uL BL + aR uR BR - (dR BR - dL BL) - B_n (aL vL + aR vR), each
+ * edge flux taking the mean coefficients of the two faces it crosses; it needs
+ * MHD_HLLD and 21 more arrays of one field. */
+typedef enum {
+  MHD_EMF_EC = 0,
+  MHD_EMF_E0 = 1,
+  MHD_EMF_ARITH = 2,
+  MHD_EMF_UCT_HLL = 3,
+  MHD_EMF_UCT_HLLD = 4
+} mhd_emf;
 /* Reconstructions of Sec. 2.3, all on the primitives: van Leer PLM (default),
  * the compact third-order LimO3 limiter (Cada & Torrilhon 2009), and PPM
  * (Colella & Woodward 1984) with the extremum-preserving limiter of Colella &
@@ -125,9 +136,10 @@ typedef struct {
 } mhd_diag;
 
 /* Device bytes a context with these parameters needs (only the grid, precision,
- * integrator and ct fields are read): two state buffers of 8 fields (11 with
- * MHD_CT_VECPOT), three buffers for MHD_RK3, plus under 1 MB of scalars and
- * partial sums.  Returns 0 if the grid is invalid. */
+ * integrator, emf and ct fields are read): two state buffers of 8 fields (11
+ * with MHD_CT_VECPOT), three buffers for MHD_RK3, the edge-solve arrays of
+ * MHD_EMF_UCT_HLL (15 fields) or MHD_EMF_UCT_HLLD (21), plus under 1 MB of
+ * scalars and partial sums.  Returns 0 if the grid is invalid. */
 size_t mhd_workspace_bytes(const mhd_params* params);
 
 /* Validate params and build a context on the borrowed workspace.  *out receives

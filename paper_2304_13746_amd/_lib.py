@@ -21,7 +21,7 @@ MHD_ERR_UNSUPPORTED = -5
 
 MHD_FP64, MHD_FP32 = 0, 1
 MHD_HLLD, MHD_HLL, MHD_HLLC = 0, 1, 2
-MHD_EMF_EC, MHD_EMF_E0, MHD_EMF_ARITH, MHD_EMF_UCT_HLL = 0, 1, 2, 3
+MHD_EMF_EC, MHD_EMF_E0, MHD_EMF_ARITH, MHD_EMF_UCT_HLL, MHD_EMF_UCT_HLLD = 0, 1, 2, 3, 4
 MHD_PLM, MHD_LIMO3, MHD_PPM = 0, 1, 2
 MHD_CT_FACE, MHD_CT_VECPOT = 0, 1
 MHD_RK2, MHD_EULER, MHD_RK3 = 0, 1, 2

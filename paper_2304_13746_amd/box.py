@@ -19,7 +19,8 @@ FIELDS = ("rho", "mx", "my", "mz", "en", "bx", "by", "bz")
 PRECISION = {"fp64": L.MHD_FP64, "fp32": L.MHD_FP32}
 RIEMANN = {"hlld": L.MHD_HLLD, "hll": L.MHD_HLL, "hllc": L.MHD_HLLC}
 INTEGRATOR = {"rk2": L.MHD_RK2, "euler": L.MHD_EULER, "rk3": L.MHD_RK3}
-EMF = {"ec": L.MHD_EMF_EC, "e0": L.MHD_EMF_E0, "arith": L.MHD_EMF_ARITH, "uct_hll": L.MHD_EMF_UCT_HLL}
+EMF = {"ec": L.MHD_EMF_EC, "e0": L.MHD_EMF_E0, "arith": L.MHD_EMF_ARITH, "uct_hll": L.MHD_EMF_UCT_HLL,
+       "uct_hlld": L.MHD_EMF_UCT_HLLD}
 RECON = {"plm": L.MHD_PLM, "limo3": L.MHD_LIMO3, "ppm": L.MHD_PPM}
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
 

@@ -24,7 +24,7 @@ struct mhd_ctx {
   int nbuf;
   int nfield;  // fields per buffer: 8, or 11 with the vector-potential form
   int cur;           // buffer holding the state
-  void* uct;         // UCT-HLL scratch (kUctArrays arrays of one field), or null
+  void* uct;         // edge-solve scratch (UCT-HLL, UCT-HLLD), or null
   Scalars* sc;       // device scalars
   BoxDesc* desc;     // device copy of this box's descriptor
   double* diag_part; // per-block diagnostic partials
@@ -59,7 +59,9 @@ size_t field_bytes(const mhd_params* p) {
 int nbuf_of(const mhd_params* p) { return p->integrator == MHD_RK3 ? 3 : 2; }
 int nfield_of(const mhd_params* p) { return p->ct == MHD_CT_VECPOT ? 11 : 8; }
 // scratch arrays of one field each: the UCT-HLL face data and edge EMFs
-int nscratch_of(const mhd_params* p) { return p->emf == MHD_EMF_UCT_HLL ? kUctArrays : 0; }
+int nscratch_of(const mhd_params* p) {
+  return p->emf == MHD_EMF_UCT_HLL ? kUctArrays : p->emf == MHD_EMF_UCT_HLLD ? kUctHlldArrays : 0;
+}
 
 // ---- cycle control kernels (one thread): everything stays on the device
 
@@ -343,6 +345,7 @@ hipError_t launch_uct(mhd_ctx* const* c, const Roles* r, int n, int mode, double
     ba.mode = mode;
     ba.w = w;
     ba.w0 = w0;
+    ba.emf = c[i0]->p.emf;
     int g = 0;
     for (int i = 0; i < m; ++i) {
       ba.desc[i] = c[i0 + i]->desc;
@@ -428,7 +431,7 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
   if (launch_ctl(true, act, m, ts, st) != hipSuccess) return MHD_ERR_HIP;
   const int integ = c[0]->p.integrator;
   const bool vp = c[0]->p.ct == MHD_CT_VECPOT;
-  const bool uct = c[0]->p.emf == MHD_EMF_UCT_HLL;
+  const bool uct = c[0]->p.emf == MHD_EMF_UCT_HLL || c[0]->p.emf == MHD_EMF_UCT_HLLD;
   for (int cyc = 0; cyc < maxs; ++cyc) {
     m = 0;
     for (int i = 0; i < n; ++i)
@@ -576,11 +579,13 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
   if (p->riemann != MHD_HLLD && p->riemann != MHD_HLL && p->riemann != MHD_HLLC)
     return MHD_ERR_INVALID_ARG;
   if (p->emf != MHD_EMF_EC && p->emf != MHD_EMF_E0 && p->emf != MHD_EMF_ARITH &&
-      p->emf != MHD_EMF_UCT_HLL)
+      p->emf != MHD_EMF_UCT_HLL && p->emf != MHD_EMF_UCT_HLLD)
     return MHD_ERR_UNSUPPORTED;
   // UCT-HLL is built for the MHD solvers (with the potential form under its
   // FP64 rule below)
   if (p->emf == MHD_EMF_UCT_HLL && p->riemann == MHD_HLLC) return MHD_ERR_UNSUPPORTED;
+  // UCT-HLLD takes its coefficients from the HLLD solve of each face
+  if (p->emf == MHD_EMF_UCT_HLLD && p->riemann != MHD_HLLD) return MHD_ERR_UNSUPPORTED;
   if (p->recon != MHD_PLM && p->recon != MHD_LIMO3 && p->recon != MHD_PPM)
     return MHD_ERR_UNSUPPORTED;
   if (p->ct != MHD_CT_FACE && p->ct != MHD_CT_VECPOT) return MHD_ERR_INVALID_ARG;

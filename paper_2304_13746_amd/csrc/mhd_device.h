@@ -426,6 +426,99 @@ __device__ __forceinline__ void flux_hllc(R gamma, R igm1, Prim<R> l, Prim<R> r,
   for (int q = 0; q < 7; ++q) f[q] = c.f[q] + sk * (us[q] - c.u[q]);
 }
 
+// UCT-HLLD coefficients of one face (Sec. 2.4, the HLLD 2D Riemann solver of
+// Mignone & Del Zanna 2021): the HLLD flux of either tangential field component
+// written as aL u_L B_L + aR u_R B_R - (dR B_R - dL B_L) - B_n (aL v_L + aR v_R).
+// With B*_a = chi_a B_a, v*_a = v_a - tv_a B_a and
+// B** = betaL B_L + betaR B_R + g (v_R - v_L), matching coefficients region by
+// region of the fan (chosen by the same tests as flux_hlld) gives
+//   L: (1, 0, 0, 0)   *L: (1, 0, S_L (chi_L - 1), 0)
+//   R: (0, 1, 0, 0)   *R: (0, 1, 0, -S_R (chi_R - 1))
+//   **L: aR = -S*_L sqL sqR / ((sqL + sqR) |B_n|), aL = 1 - aR,
+//        dL = u_L + S_L (chi_L - 1) + S*_L (betaL - chi_L) - aL u_L,
+//        dR = aR u_R - S*_L betaR
+//   **R: aL = S*_R sqL sqR / ((sqL + sqR) |B_n|), aR = 1 - aL,
+//        dL = S*_R betaL - aL u_L,
+//        dR = aR u_R - (u_R + S_R (chi_R - 1) + S*_R (betaR - chi_R)).
+template <typename R>
+__device__ __forceinline__ void hlld_uct_coef(R gamma, const Prim<R>& l, const Prim<R>& r, R bn,
+                                              R& al, R& ar, R& dl_, R& dr_) {
+  R sl, sr, cmax;
+  outer_speeds(gamma, l, r, bn, sl, sr, cmax);
+  dl_ = R(0);
+  dr_ = R(0);
+  if (sl >= R(0)) {
+    al = R(1);
+    ar = R(0);
+    return;
+  }
+  if (sr <= R(0)) {
+    al = R(0);
+    ar = R(1);
+    return;
+  }
+  const R bb_l = (bn * bn + l.b1 * l.b1) + l.b2 * l.b2;
+  const R bb_r = (bn * bn + r.b1 * r.b1) + r.b2 * r.b2;
+  const R ptl = l.p + R(0.5) * bb_l, ptr = r.p + R(0.5) * bb_r;
+  const R dl = (sl - l.un) * l.rho;
+  const R dr = (sr - r.un) * r.rho;
+  const R iden = rcp(dr - dl);
+  const R sm = (((dr * r.un - dl * l.un) - ptr) + ptl) * iden;
+  R rhos[2], chi[2], tv[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const Prim<R>& w = a == 0 ? l : r;
+    const R sua = (a == 0 ? sl : sr) - w.un;
+    const R da = sua * w.rho;
+    const R sam = (a == 0 ? sl : sr) - sm;
+    const R isam = rcp(sam);
+    rhos[a] = da * isam;
+    const R t = da * sam;
+    const R bn2 = bn * bn;
+    const R den = t - bn2;
+    if (dabs(den) <= Tol<R>::degen * (dabs(t) + bn2)) {
+      chi[a] = R(1);
+      tv[a] = R(0);
+    } else {
+      const R idn = rcp(den);
+      tv[a] = (bn * (sm - w.un)) * idn;
+      chi[a] = (da * sua - bn2) * idn;
+    }
+  }
+  const R sql = dsqrt(rhos[0]), sqr = dsqrt(rhos[1]);
+  const R abn = dabs(bn);
+  const R ssl = sm - dvd(abn, sql);
+  const R ssr = sm + dvd(abn, sqr);
+  if (ssl >= R(0)) {
+    al = R(1);
+    ar = R(0);
+    dl_ = sl * (chi[0] - R(1));
+    return;
+  }
+  if (!(sm >= R(0)) && !(ssr >= R(0))) {
+    al = R(0);
+    ar = R(1);
+    dr_ = -(sr * (chi[1] - R(1)));
+    return;
+  }
+  const R sgn = bn > R(0) ? R(1) : (bn < R(0) ? R(-1) : R(0));
+  const R isq = rcp(sql + sqr);
+  const R pq = sql * sqr;
+  const R betal = (sqr * chi[0] + pq * (sgn * tv[0])) * isq;
+  const R betar = (sql * chi[1] - pq * (sgn * tv[1])) * isq;
+  if (sm >= R(0)) {
+    ar = dvd(-(ssl * (pq * isq)), abn);
+    al = R(1) - ar;
+    dl_ = ((l.un + sl * (chi[0] - R(1))) + ssl * (betal - chi[0])) - al * l.un;
+    dr_ = ar * r.un - ssl * betar;
+  } else {
+    al = dvd(ssr * (pq * isq), abn);
+    ar = R(1) - al;
+    dl_ = ssr * betal - al * l.un;
+    dr_ = ar * r.un - ((r.un + sr * (chi[1] - R(1))) + ssr * (betar - chi[1]));
+  }
+}
+
 enum { SOLVER_HLLD = 0, SOLVER_HLL = 1, SOLVER_HLLC = 2 };
 
 template <int SOLVER, typename R>
@@ -443,7 +536,8 @@ __device__ __forceinline__ void riemann(R gamma, R igm1, const Prim<R>& l, const
 // derivative terms by the sign of the face mass flux, E^0 averages the two
 // candidates on every side, the arithmetic scheme is the mean of the four face
 // EMFs alone.
-enum { EMF_EC = 0, EMF_E0 = 1, EMF_ARITH = 2, EMF_UCT = 3 };  // UCT: see mhd_uct.hip
+// UCT (UCT-HLL) and UCT_HLLD: edge solves, see mhd_uct.hip
+enum { EMF_EC = 0, EMF_E0 = 1, EMF_ARITH = 2, EMF_UCT = 3, EMF_UCT_HLLD = 4 };
 
 // Upwind choice by the sign of a mass flux; zero averages the two candidates.
 template <typename R>

@@ -67,9 +67,11 @@ struct BoxDesc {
   double gamma;
   double b0[3];           // mean field of the vector-potential form
   Scalars* sc;
-  // UCT-HLL scratch: 15 arrays of one cell each, ustride elements apart: per
-  // face direction d the HLL speeds alpha+, alpha- and the averaged transverse
-  // velocities vt1, vt2 (array 4 d + q), then the edge EMFs E_x, E_y, E_z
+  // edge-solve scratch, arrays of one cell each, ustride elements apart.
+  // UCT-HLL (15 arrays): per face direction d the HLL speeds alpha+, alpha- and
+  // the averaged transverse velocities vt1, vt2 (array 4 d + q), then the edge
+  // EMFs E_x, E_y, E_z.  UCT-HLLD (21): per direction the HLLD coefficients
+  // aL, aR, dL, dR and the weighted vt1, vt2 (array 6 d + q), then the EMFs.
   void* uct;
   long long ustride;
 };
@@ -133,9 +135,11 @@ __host__ __device__ __forceinline__ int wrap_index(int v, int n) {
 
 // UCT-HLL after a stage launch: the edge EMFs from the face data the stage
 // kernel exported, then the face-field update B_dst = w (B_src - dt curl E) +
-// w0 B_base.  ba.start[] counts blocks of kUctBlock cells.
+// w0 B_base.  ba.start[] counts blocks of kUctBlock cells; ba.emf selects
+// UCT-HLL (3) or UCT-HLLD (4).
 constexpr int kUctBlock = 256;
-constexpr int kUctArrays = 15;
+constexpr int kUctArrays = 15;      // UCT-HLL
+constexpr int kUctHlldArrays = 21;  // UCT-HLLD
 // (with update_b = false only the edge EMFs: the potential form takes them)
 hipError_t uct_f64(const BatchArgs& b, int recon, bool update_b, hipStream_t st);
 hipError_t uct_f32(const BatchArgs& b, int recon, bool update_b, hipStream_t st);

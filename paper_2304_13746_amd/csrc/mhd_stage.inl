@@ -191,10 +191,14 @@ struct Face {
   R cons[5];  // grid-frame flux of rho, mx, my, mz, E
   R fb1, fb2; // face-frame fluxes of B_t1, B_t2
   R cmax;
-  R ap, am, vt1, vt2;  // UCT-HLL: HLL speeds and averaged transverse velocities
+  // edge-solve face data: UCT-HLL the HLL speeds (ap, am); UCT-HLLD the HLLD
+  // coefficients (ap = aL, am = aR, dl, dr); both the weighted transverse
+  // velocities vt1, vt2
+  R ap, am, dl, dr, vt1, vt2;
 };
 
-template <int D, int SOLVER, bool UCT = false, typename R>
+// UCT = 0: no edge-solve data; EMF_UCT (UCT-HLL) or EMF_UCT_HLLD
+template <int D, int SOLVER, int UCT = 0, typename R>
 __device__ __forceinline__ void solve_face(const StageArgs<R>& a, const R* ql, const R* qr, R bn,
                                            Face<R>& out) {
   R f[7];
@@ -203,7 +207,7 @@ __device__ __forceinline__ void solve_face(const StageArgs<R>& a, const R* ql, c
   to_grid<D>(f, out.cons);
   out.fb1 = f[5];
   out.fb2 = f[6];
-  if constexpr (UCT) {
+  if constexpr (UCT == EMF_UCT) {
     // alpha+ = max(0, S_R), alpha- = max(0, -S_L) of the outer bounds and the
     // transverse velocities averaged with the HLL weights
     R sl, sr, cm;
@@ -214,17 +218,34 @@ __device__ __forceinline__ void solve_face(const StageArgs<R>& a, const R* ql, c
     out.am = am;
     out.vt1 = dvd(ap * l.v1 + am * r.v1, ap + am);
     out.vt2 = dvd(ap * l.v2 + am * r.v2, ap + am);
+  } else if constexpr (UCT == EMF_UCT_HLLD) {
+    // the HLLD coefficients and the transverse velocities they weight
+    hlld_uct_coef(a.gamma, l, r, bn, out.ap, out.am, out.dl, out.dr);
+    out.vt1 = out.ap * l.v1 + out.am * r.v1;
+    out.vt2 = out.ap * l.v2 + out.am * r.v2;
   }
 }
 
-// UCT-HLL face data of a face solved by its owner, stored at the face's cell
-template <int D, typename R>
+// edge-solve face data of a face solved by its owner, stored at the face's
+// cell: UCT-HLL arrays 4 D + (ap, am, vt1, vt2), UCT-HLLD 6 D + (aL, aR, dL, dR,
+// vt1, vt2)
+template <int D, int UCT, typename R>
 __device__ __forceinline__ void put_uct(const StageArgs<R>& a, long long o, const Face<R>& f) {
-  R* u = a.uf + (long long)(4 * D) * a.ustride + o;
-  gst(u, 0, f.ap);
-  gst(u, a.ustride, f.am);
-  gst(u, 2 * a.ustride, f.vt1);
-  gst(u, 3 * a.ustride, f.vt2);
+  if constexpr (UCT == EMF_UCT_HLLD) {
+    R* u = a.uf + (long long)(6 * D) * a.ustride + o;
+    gst(u, 0, f.ap);
+    gst(u, a.ustride, f.am);
+    gst(u, 2 * a.ustride, f.dl);
+    gst(u, 3 * a.ustride, f.dr);
+    gst(u, 4 * a.ustride, f.vt1);
+    gst(u, 5 * a.ustride, f.vt2);
+  } else {
+    R* u = a.uf + (long long)(4 * D) * a.ustride + o;
+    gst(u, 0, f.ap);
+    gst(u, a.ustride, f.am);
+    gst(u, 2 * a.ustride, f.vt1);
+    gst(u, 3 * a.ustride, f.vt2);
+  }
 }
 
 // Tile geometry: TX x TY interior, threads own interior columns then the ring.
@@ -417,10 +438,12 @@ stage_kernel(BatchArgs ba) {
   // field is written as zero, and the ring columns solve only the x- and
   // y-faces the tile's own cells need
   constexpr bool HY = SOLVER == SOLVER_HLLC;
-  // UCT-HLL forms its edge EMFs in launches of its own: this kernel exports the
+  // the edge solves (UCT-HLL, UCT-HLLD) form their EMFs in launches of their
+  // own: this kernel exports the
   // face data they need and, like the hydrodynamic path, does no corner-EMF work
   // and solves only the faces the tile's own cells need (it leaves B alone)
-  constexpr bool UCT = EMF == EMF_UCT;
+  constexpr bool UCT = EMF == EMF_UCT || EMF == EMF_UCT_HLLD;
+  constexpr int UK = UCT ? EMF : 0;  // which edge solve's face data to export
   constexpr bool NE = HY || UCT;
   // FP64 PPM limits each cell's x and y faces once per plane into LDS (FP32 PPM
   // limits them per face: the extra 15 KB of LDS would cost it a block per CU,
@@ -688,14 +711,14 @@ stage_kernel(BatchArgs ba) {
           bn = gld(a.src[5], (long long)km * plane + col);
         }
       }
-      solve_face<0, SOLVER, UCT>(a, ql, qr, bn, fx);
+      solve_face<0, SOLVER, UK>(a, ql, qr, bn, fx);
       // the previous plane's exports were consumed before the last barrier
       if constexpr (NE) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) S.xcons[q][ex_me] = fx.cons[q];
         S.xcmax[ex_me] = fx.cmax;
         if constexpr (UCT) {
-          if (real && m >= z0 && m < z1) put_uct<0>(a, (long long)km * plane + col, fx);
+          if (real && m >= z0 && m < z1) put_uct<0, UK>(a, (long long)km * plane + col, fx);
         }
       } else if (corner_x) {
         const int ec = T::e(TX, -1);
@@ -741,13 +764,13 @@ stage_kernel(BatchArgs ba) {
           bn = gld(a.src[6], (long long)km * plane + col);
         }
       }
-      solve_face<1, SOLVER, UCT>(a, ql, qr, bn, fy);
+      solve_face<1, SOLVER, UK>(a, ql, qr, bn, fy);
       if constexpr (NE) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) S.ycons[q][ex_me] = fy.cons[q];
         S.ycmax[ex_me] = fy.cmax;
         if constexpr (UCT) {
-          if (real && m >= z0 && m < z1) put_uct<1>(a, (long long)km * plane + col, fy);
+          if (real && m >= z0 && m < z1) put_uct<1, UK>(a, (long long)km * plane + col, fy);
         }
       } else if (corner_y) {
         const int ec = T::e(-1, TY);
@@ -829,9 +852,9 @@ stage_kernel(BatchArgs ba) {
           qa[v] = hi;  // becomes top of cell m
         }
       }
-      if (m >= z0) solve_face<2, SOLVER, UCT>(a, top7, bot, bz_m, fz);
+      if (m >= z0) solve_face<2, SOLVER, UK>(a, top7, bot, bz_m, fz);
       if constexpr (UCT) {
-        if (real && m >= z0 && m < z1) put_uct<2>(a, (long long)km * plane + col, fz);
+        if (real && m >= z0 && m < z1) put_uct<2, UK>(a, (long long)km * plane + col, fz);
       }
 #pragma unroll
       for (int v = 0; v < 7; ++v) {
@@ -1038,11 +1061,15 @@ static hipError_t launch_mode(const BatchArgs& ba, hipStream_t st, bool prepare)
 // The vector-potential form is built for FP64, with every EMF scheme.
 template <typename R, int SOLVER, int RECON, int TX, int TY>
 static hipError_t launch_emf(const BatchArgs& ba, hipStream_t st, bool prepare) {
-  if (ba.emf == EMF_UCT) {
-    // UCT-HLL: the stage kernel leaves the field to the edge-solve launches,
-    // so one build serves both CT forms (the potential form in FP64)
-    if (ba.ct == CT_FACE || (ba.ct == CT_VECPOT && sizeof(R) == 8))
+  if (ba.emf == EMF_UCT || ba.emf == EMF_UCT_HLLD) {
+    // UCT-HLL, UCT-HLLD: the stage kernel leaves the field to the edge-solve
+    // launches, so one build serves both CT forms (the potential form in FP64)
+    if (!(ba.ct == CT_FACE || (ba.ct == CT_VECPOT && sizeof(R) == 8))) return hipErrorInvalidValue;
+    if (ba.emf == EMF_UCT)
       return launch_mode<R, SOLVER, RECON, EMF_UCT, CT_FACE, TX, TY>(ba, st, prepare);
+    // UCT-HLLD takes its coefficients from the HLLD solve
+    if constexpr (SOLVER == SOLVER_HLLD)
+      return launch_mode<R, SOLVER, RECON, EMF_UCT_HLLD, CT_FACE, TX, TY>(ba, st, prepare);
     return hipErrorInvalidValue;
   }
   if (ba.ct == CT_VECPOT) {  // the potential form is built for FP64

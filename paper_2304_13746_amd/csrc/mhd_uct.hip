@@ -1,7 +1,13 @@
-// mhd_uct.hip -- UCT-HLL corner EMFs (Lesur et al. 2023, Sec. 2.4: the scheme
-// class that solves a 2D Riemann problem at each cell edge, after Londrillo &
-// Del Zanna 2004, in the form of Mignone & Del Zanna 2021) and the face-field
-// update that follows them.
+// mhd_uct.hip -- UCT-HLL and UCT-HLLD corner EMFs (Lesur et al. 2023, Sec. 2.4:
+// the scheme class that solves a 2D Riemann problem at each cell edge, after
+// Londrillo & Del Zanna 2004, in the form of Mignone & Del Zanna 2021) and the
+// face-field update that follows them.
+//
+// UCT-HLLD runs the same two launches with the HLLD coefficients (aL, aR, dL,
+// dR) each face exports instead of the HLL speeds: the 1D flux across an edge
+// is aL vL bL + aR vR bR - (dR bR - dL bL) with each coefficient the mean of
+// the two faces that share the edge, and the transverse velocities weighted
+// by aL, aR.
 //
 // A stage with this scheme runs the fused stage kernel, which updates U and
 // exports, for every face, the HLL speeds alpha+ = max(0, S_R), alpha- =
@@ -30,8 +36,19 @@ namespace mhd {
 namespace {
 
 enum { F_BX = 5 };
-// face-data arrays: 4 d + {alpha+, alpha-, vt1, vt2}; then E_x, E_y, E_z
-enum { U_AP = 0, U_AM = 1, U_VT1 = 2, U_VT2 = 3, U_E = 12 };
+// face-data arrays, UCT-HLL: 4 d + {alpha+, alpha-, vt1, vt2}, then E_x, E_y,
+// E_z (12, 13, 14); UCT-HLLD: 6 d + {aL, aR, dL, dR, vt1, vt2}, then the EMFs
+// (18, 19, 20)
+template <int SCH>
+struct Layout;
+template <>
+struct Layout<EMF_UCT> {
+  enum { PER = 4, A0 = 0, A1 = 1, VT1 = 2, VT2 = 3, E = 12 };
+};
+template <>
+struct Layout<EMF_UCT_HLLD> {
+  enum { PER = 6, A0 = 0, A1 = 1, D0 = 2, D1 = 3, VT1 = 4, VT2 = 5, E = 18 };
+};
 
 __device__ __forceinline__ int box_of(const BatchArgs& ba, int b) {
   int box = 0;
@@ -52,6 +69,11 @@ __device__ __forceinline__ R rmax(R a, R b) {
 template <typename R>
 __device__ __forceinline__ R uct_part(R ap, R am, R vl, R bl, R vr, R br) {
   return dvd((ap * (vl * bl) + am * (vr * br)) - (ap * am) * (br - bl), ap + am);
+}
+
+template <typename R>
+__device__ __forceinline__ R uct_part_d(R al, R ar, R dl, R dr, R vl, R bl, R vr, R br) {
+  return (al * (vl * bl) + ar * (vr * br)) - (dr * br - dl * bl);
 }
 
 // face values along the line through an edge: four (the three-cell limiters)
@@ -77,10 +99,14 @@ __device__ __forceinline__ void to_edge(const R* q, R& lo_side, R& hi_side) {
   }
 }
 
-// the 1D HLL flux across one edge from the face values of b and v along the
-// line through it (indices o[0 .. kLine-1]) and the speeds of the faces it crosses
-template <int RECON, typename R>
-__device__ __forceinline__ R edge_flux(const R* b, const R* v, const long long* o, R ap, R am) {
+// the 1D flux across one edge from the face values of b and v along the line
+// through it (indices o[0 .. kLine-1]) and the face data of the two faces it
+// crosses (f1, f2 in the arrays of face direction dir): UCT-HLL with their
+// larger speeds, UCT-HLLD with their mean coefficients
+template <int SCH, int RECON, typename R, typename FA>
+__device__ __forceinline__ R edge_flux(const R* b, const R* v, const long long* o, FA fa, int dir,
+                                       long long f1, long long f2) {
+  using Lt = Layout<SCH>;
   constexpr int NQ = kLine<RECON>;
   R bq[NQ], vq[NQ];
 #pragma unroll
@@ -91,11 +117,21 @@ __device__ __forceinline__ R edge_flux(const R* b, const R* v, const long long* 
   R bl, br, vl, vr;
   to_edge<RECON>(bq, bl, br);
   to_edge<RECON>(vq, vl, vr);
-  return uct_part(ap, am, vl, bl, vr, br);
+  if constexpr (SCH == EMF_UCT_HLLD) {
+    const R al = R(0.5) * (ld(fa(dir, Lt::A0), f1) + ld(fa(dir, Lt::A0), f2));
+    const R ar = R(0.5) * (ld(fa(dir, Lt::A1), f1) + ld(fa(dir, Lt::A1), f2));
+    const R dl = R(0.5) * (ld(fa(dir, Lt::D0), f1) + ld(fa(dir, Lt::D0), f2));
+    const R dr = R(0.5) * (ld(fa(dir, Lt::D1), f1) + ld(fa(dir, Lt::D1), f2));
+    return uct_part_d(al, ar, dl, dr, vl, bl, vr, br);
+  } else {
+    return uct_part(rmax(ld(fa(dir, Lt::A0), f1), ld(fa(dir, Lt::A0), f2)),
+                    rmax(ld(fa(dir, Lt::A1), f1), ld(fa(dir, Lt::A1), f2)), vl, bl, vr, br);
+  }
 }
 
-template <typename R, int RECON>
+template <typename R, int RECON, int SCH>
 __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
+  using Lt = Layout<SCH>;
   const int box = box_of(ba, blockIdx.x);
   const BoxDesc* d = ba.desc[box];
   const int nx = d->nx, ny = d->ny, nz = d->nz;
@@ -114,46 +150,41 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_emf(BatchArgs ba) {
   const R* bz = static_cast<const R*>(d->buf[si][F_BX + 2]);
   R* u = static_cast<R*>(d->uct);
   const long long us = d->ustride;
-  auto fa = [&](int dir, int q) -> const R* { return u + (long long)(4 * dir + q) * us; };
+  auto fa = [&](int dir, int q) -> const R* { return u + (long long)(Lt::PER * dir + q) * us; };
   constexpr int NQ = kLine<RECON>, Q0 = NQ / 2;  // line offsets -Q0 .. NQ-Q0-1
   long long o[NQ];
   // E_z at (i-1/2, j-1/2, k): P = x, Q = y
   {
     const long long cjm = yj(-1), cim = xi(-1);
     for (int q = 0; q < NQ; ++q) o[q] = xi(q - Q0);  // y-faces along x around i-1/2
-    const R fp = edge_flux<RECON>(by, fa(1, U_VT2), o, rmax(ld(fa(0, U_AP), cjm), ld(fa(0, U_AP), c)),
-                           rmax(ld(fa(0, U_AM), cjm), ld(fa(0, U_AM), c)));
+    const R fp = edge_flux<SCH, RECON>(by, fa(1, Lt::VT2), o, fa, 0, cjm, c);
     for (int q = 0; q < NQ; ++q) o[q] = yj(q - Q0);  // x-faces along y around j-1/2
-    const R fq = edge_flux<RECON>(bx, fa(0, U_VT1), o, rmax(ld(fa(1, U_AP), cim), ld(fa(1, U_AP), c)),
-                           rmax(ld(fa(1, U_AM), cim), ld(fa(1, U_AM), c)));
-    u[(U_E + 2) * us + c] = fq - fp;
+    const R fq = edge_flux<SCH, RECON>(bx, fa(0, Lt::VT1), o, fa, 1, cim, c);
+    u[(Lt::E + 2) * us + c] = fq - fp;
   }
   // E_x at (i, j-1/2, k-1/2): P = y, Q = z
   {
     const long long ckm = zk(-1), cjm = yj(-1);
     for (int q = 0; q < NQ; ++q) o[q] = yj(q - Q0);  // z-faces along y around j-1/2
-    const R fp = edge_flux<RECON>(bz, fa(2, U_VT2), o, rmax(ld(fa(1, U_AP), ckm), ld(fa(1, U_AP), c)),
-                           rmax(ld(fa(1, U_AM), ckm), ld(fa(1, U_AM), c)));
+    const R fp = edge_flux<SCH, RECON>(bz, fa(2, Lt::VT2), o, fa, 1, ckm, c);
     for (int q = 0; q < NQ; ++q) o[q] = zk(q - Q0);  // y-faces along z around k-1/2
-    const R fq = edge_flux<RECON>(by, fa(1, U_VT1), o, rmax(ld(fa(2, U_AP), cjm), ld(fa(2, U_AP), c)),
-                           rmax(ld(fa(2, U_AM), cjm), ld(fa(2, U_AM), c)));
-    u[U_E * us + c] = fq - fp;
+    const R fq = edge_flux<SCH, RECON>(by, fa(1, Lt::VT1), o, fa, 2, cjm, c);
+    u[Lt::E * us + c] = fq - fp;
   }
   // E_y at (i-1/2, j, k-1/2): P = z, Q = x
   {
     const long long cim = xi(-1), ckm = zk(-1);
     for (int q = 0; q < NQ; ++q) o[q] = zk(q - Q0);  // x-faces along z around k-1/2
-    const R fp = edge_flux<RECON>(bx, fa(0, U_VT2), o, rmax(ld(fa(2, U_AP), cim), ld(fa(2, U_AP), c)),
-                           rmax(ld(fa(2, U_AM), cim), ld(fa(2, U_AM), c)));
+    const R fp = edge_flux<SCH, RECON>(bx, fa(0, Lt::VT2), o, fa, 2, cim, c);
     for (int q = 0; q < NQ; ++q) o[q] = xi(q - Q0);  // z-faces along x around i-1/2
-    const R fq = edge_flux<RECON>(bz, fa(2, U_VT1), o, rmax(ld(fa(0, U_AP), ckm), ld(fa(0, U_AP), c)),
-                           rmax(ld(fa(0, U_AM), ckm), ld(fa(0, U_AM), c)));
-    u[(U_E + 1) * us + c] = fq - fp;
+    const R fq = edge_flux<SCH, RECON>(bz, fa(2, Lt::VT1), o, fa, 0, ckm, c);
+    u[(Lt::E + 1) * us + c] = fq - fp;
   }
 }
 
-template <typename R>
+template <typename R, int SCH>
 __global__ void __launch_bounds__(kUctBlock) k_uct_ct(BatchArgs ba) {
+  constexpr int U_E = Layout<SCH>::E;
   const int box = box_of(ba, blockIdx.x);
   const BoxDesc* d = ba.desc[box];
   const int nx = d->nx, ny = d->ny, nz = d->nz;
@@ -195,21 +226,29 @@ __global__ void __launch_bounds__(kUctBlock) k_uct_ct(BatchArgs ba) {
   bd[2][c] = bzn;
 }
 
-template <typename R>
-hipError_t uct_launch(const BatchArgs& ba, int recon, bool update_b, hipStream_t st) {
-  if (ba.nbox < 1 || ba.nbox > kMaxBatch || ba.total < 1) return hipErrorInvalidValue;
+template <typename R, int SCH>
+hipError_t uct_launch_s(const BatchArgs& ba, int recon, bool update_b, hipStream_t st) {
   if (recon == RECON_PPM)
-    hipLaunchKernelGGL((k_uct_emf<R, RECON_PPM>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
+    hipLaunchKernelGGL((k_uct_emf<R, RECON_PPM, SCH>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
   else if (recon == RECON_LIMO3)
-    hipLaunchKernelGGL((k_uct_emf<R, RECON_LIMO3>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
+    hipLaunchKernelGGL((k_uct_emf<R, RECON_LIMO3, SCH>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
   else if (recon == RECON_PLM)
-    hipLaunchKernelGGL((k_uct_emf<R, RECON_PLM>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
+    hipLaunchKernelGGL((k_uct_emf<R, RECON_PLM, SCH>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
   else
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !update_b) return e;
-  hipLaunchKernelGGL(k_uct_ct<R>, dim3(ba.total), dim3(kUctBlock), 0, st, ba);
+  hipLaunchKernelGGL((k_uct_ct<R, SCH>), dim3(ba.total), dim3(kUctBlock), 0, st, ba);
   return hipGetLastError();
+}
+
+// ba.emf selects the scheme (EMF_UCT: UCT-HLL, EMF_UCT_HLLD)
+template <typename R>
+hipError_t uct_launch(const BatchArgs& ba, int recon, bool update_b, hipStream_t st) {
+  if (ba.nbox < 1 || ba.nbox > kMaxBatch || ba.total < 1) return hipErrorInvalidValue;
+  if (ba.emf == EMF_UCT_HLLD) return uct_launch_s<R, EMF_UCT_HLLD>(ba, recon, update_b, st);
+  if (ba.emf == EMF_UCT) return uct_launch_s<R, EMF_UCT>(ba, recon, update_b, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace

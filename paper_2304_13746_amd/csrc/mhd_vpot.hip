@@ -35,12 +35,13 @@ __global__ void __launch_bounds__(kVpotBlock) k_vpot_update(BatchArgs ba) {
   if (c >= n) return;
   const double dt = ld_agent(&d->sc->dt);
   const int si = ba.src[box], di = ba.dst[box], bi = ba.base[box];
-  // the edge EMFs: in the output's face-field slots, or (UCT-HLL) in the
-  // edge-EMF scratch arrays 12 .. 14
-  const bool uct = ba.emf == EMF_UCT;
+  // the edge EMFs: in the output's face-field slots, or (edge solves) in the
+  // edge-EMF scratch arrays, 12 .. 14 (UCT-HLL) or 18 .. 20 (UCT-HLLD)
+  const bool uct = ba.emf == EMF_UCT || ba.emf == EMF_UCT_HLLD;
+  const int e0 = ba.emf == EMF_UCT_HLLD ? 18 : 12;
   for (int f = 0; f < 3; ++f) {
     const double* as = static_cast<const double*>(d->buf[si][F_AX + f]);
-    const double* e = uct ? static_cast<const double*>(d->uct) + (12 + f) * d->ustride
+    const double* e = uct ? static_cast<const double*>(d->uct) + (e0 + f) * d->ustride
                           : static_cast<const double*>(d->buf[di][F_BX + f]);
     const double* ab = static_cast<const double*>(d->buf[bi][F_AX + f]);
     double* ad = static_cast<double*>(d->buf[di][F_AX + f]);

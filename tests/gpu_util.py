@@ -34,7 +34,8 @@ def oracle_params(dims, l=(1.0, 1.0, 1.0), riemann="hlld", integrator="rk2", gam
     return O.Params(nx, ny, nz, *l, gamma=gamma, cfl=cfl,
                     riemann={"hlld": O.HLLD, "hll": O.HLL, "hllc": O.HLLC}[riemann],
                     integrator={"rk2": O.RK2, "euler": O.EULER, "rk3": O.RK3}[integrator],
-                    emf={"ec": O.EMF_EC, "e0": O.EMF_E0, "arith": O.EMF_ARITH, "uct_hll": O.EMF_UCT_HLL}[emf],
+                    emf={"ec": O.EMF_EC, "e0": O.EMF_E0, "arith": O.EMF_ARITH, "uct_hll": O.EMF_UCT_HLL,
+                         "uct_hlld": O.EMF_UCT_HLLD}[emf],
                     recon={"plm": O.PLM, "limo3": O.LIMO3, "ppm": O.PPM}[recon])
 
 

@@ -76,9 +76,20 @@ def test_workspace_bytes_and_argument_checks():
                {"emf": "e0", "ct": "vecpot"}, {"emf": "arith", "ct": "vecpot", "riemann": "hll"}):
         q = make_params(8, 8, 8, **kw)  # accepted up to the (missing) workspace
         assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE, kw
-    # UCT-HLL takes 15 more arrays of one field in the workspace
+    # UCT-HLL takes 15 more arrays of one field in the workspace, UCT-HLLD 21
     pu = make_params(32, 32, 32, precision="fp64", emf="uct_hll")
     assert L.mhd_workspace_bytes(C.byref(pu)) - n64 == 15 * 32 ** 3 * 8
+    pu = make_params(32, 32, 32, precision="fp64", emf="uct_hlld")
+    assert L.mhd_workspace_bytes(C.byref(pu)) - n64 == 21 * 32 ** 3 * 8
+    # UCT-HLLD takes its coefficients from the HLLD solve
+    for kw in ({"emf": "uct_hlld", "riemann": "hll"}, {"emf": "uct_hlld", "riemann": "hllc"},
+               {"emf": "uct_hlld", "ct": "vecpot", "precision": "fp32"}):
+        q = make_params(8, 8, 8, **kw)
+        assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_UNSUPPORTED, kw
+    for kw in ({"emf": "uct_hlld"}, {"emf": "uct_hlld", "precision": "fp32", "recon": "ppm"},
+               {"emf": "uct_hlld", "ct": "vecpot", "recon": "limo3"}):
+        q = make_params(8, 8, 8, **kw)
+        assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE, kw
     # no workspace / too small / misaligned
     q = make_params(8, 8, 8)
     assert L.mhd_create(C.byref(q), C.byref(ctx)) == _lib.MHD_ERR_WORKSPACE
