@@ -20,7 +20,11 @@ EXAMPLE = os.path.join(HERE, "mhd_abi_example")
 STAGE = [f"mhd_stage_{p}_{s}.hip" for p in ("f64", "f32") for s in ("hlld", "hll", "hllc")]
 SOURCES = ["mhd_api.hip", *STAGE, "mhd_vpot.hip", "mhd_uct.hip"]
 ARCH = os.environ.get("MHD_OFFLOAD_ARCH", "gfx950")
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
+# roctx markers (host side) around the library's calls, for rocprofv3 --marker-trace
+LINK = ["-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx",
+        "-Wl,-rpath," + os.path.join(ROCM, "lib")]
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall",
          "-Wno-unused-variable", "-Wno-unused-function"]
@@ -47,7 +51,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(s, defines, tag), SOURCES))
     tmp = out + ".tmp"
-    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, *LINK]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -7,6 +7,8 @@
 
 #include <mutex>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/mhd.h"
 #include "mhd_internal.h"
 
@@ -36,6 +38,15 @@ struct mhd_ctx {
 };
 
 namespace {
+
+// roctx range over a scope: host-side markers that rocprofv3 --marker-trace
+// records around the library's calls and cycles (no device work)
+struct Range {
+  explicit Range(const char* m) { roctxRangePushA(m); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 constexpr size_t kAlign = 256;
 constexpr int kDiagBlocks = 512;
@@ -418,6 +429,7 @@ hipError_t launch_ctl(bool begin, mhd_ctx* const* c, int n, const double* t_stop
 // Advance n contexts (same precision, solver, tile, integrator) by nsteps[i]
 // cycles each on one stream; every box keeps its own dt and t_stop.
 int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop, hipStream_t st) {
+  Range range("mhd cycles");
   int maxs = 0;
   for (int i = 0; i < n; ++i) maxs = nsteps[i] > maxs ? nsteps[i] : maxs;
   if (maxs == 0) return MHD_OK;
@@ -433,6 +445,7 @@ int step_group(mhd_ctx* const* c, const int* nsteps, int n, const double* t_stop
   const bool vp = c[0]->p.ct == MHD_CT_VECPOT;
   const bool uct = c[0]->p.emf == MHD_EMF_UCT_HLL || c[0]->p.emf == MHD_EMF_UCT_HLLD;
   for (int cyc = 0; cyc < maxs; ++cyc) {
+    Range cycle("mhd cycle");
     m = 0;
     for (int i = 0; i < n; ++i)
       if (nsteps[i] > cyc) { act[m] = c[i]; ts[m] = t_stop ? t_stop[i] : 0.0; ++m; }
@@ -650,6 +663,7 @@ int mhd_create(const mhd_params* p, mhd_ctx** out) {
 }
 
 int mhd_set_state(mhd_ctx* c, const mhd_state_view* v, double t, double dt_next) {
+  Range range("mhd_set_state");
   if (!c || !v) return MHD_ERR_INVALID_ARG;
   const bool vp = c->p.ct == MHD_CT_VECPOT;
   void* src[11];
@@ -687,6 +701,7 @@ int mhd_step(mhd_ctx* c, int nsteps, double t_stop) {
 }
 
 int mhd_get_state(mhd_ctx* c, const mhd_state_view* v, double* t, double* dt_next) {
+  Range range("mhd_get_state");
   if (!c) return MHD_ERR_INVALID_ARG;
   if (v) {
     void* dst[11];
@@ -730,6 +745,7 @@ int mhd_get_stage_output(mhd_ctx* c, int stage, const mhd_state_view* v) {
 }
 
 int mhd_get_diagnostics(mhd_ctx* c, mhd_diag* out) {
+  Range range("mhd_get_diagnostics");
   if (!c || !out) return MHD_ERR_INVALID_ARG;
   return diagnostics_into(c, c->diag_part, out);
 }
@@ -770,6 +786,7 @@ int mhd_get_launch(const mhd_ctx* c, int* tile, int* zchunk) {
 }
 
 int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_result* out) {
+  Range range("mhd_tune");
   if (!ctxs || n < 1 || n > 4096 || reps < 1 || reps > 100) return MHD_ERR_INVALID_ARG;
   for (int i = 0; i < n; ++i)
     if (!ctxs[i]) return MHD_ERR_INVALID_ARG;
