@@ -102,6 +102,13 @@ def lib():
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_set_num_threads.restype = None
+        L.orc_set_ppm_flip.argtypes = [C.c_double, C.c_long]
+        L.orc_set_ppm_flip.restype = None
+        L.orc_ppm_flips.restype = C.c_long
+        L.orc_ppm_sites.argtypes = [C.POINTER(C.c_long), C.c_long]
+        L.orc_ppm_sites.restype = C.c_long
+        lp = C.POINTER(C.c_long)
+        L.orc_set_ppm_pick.argtypes = [lp, lp, C.c_long, C.c_long]
         _lib = L
     return _lib
 
@@ -292,3 +299,42 @@ def num_threads() -> int:
 def set_num_threads(n: int) -> None:
     """Threads of the following oracle calls (n > 0)."""
     lib().orc_set_num_threads(int(n))
+
+
+def set_ppm_flip(band: float, target: int = -1) -> None:
+    """Test hook for lower-precision comparisons (Sec. 2.3, PPM): the PPM
+    decisions whose outcome jumps (interface value outside its cells, extremum,
+    vanishing D2) and whose test lies within ``band`` (relative to the stencil's
+    largest |a|) of the threshold are counted in the order met and taken the
+    other way: every one (target < 0) or only the target-th.  While band > 0
+    the oracle runs on one thread, so the order is deterministic; band 0
+    restores the method as written and the thread count.  Resets the count of
+    ppm_flips()."""
+    lib().orc_set_ppm_flip(float(band), int(target))
+
+
+def ppm_flips() -> int:
+    """Near PPM decisions met since the last set_ppm_flip."""
+    return int(lib().orc_ppm_flips())
+
+
+def ppm_sites() -> np.ndarray:
+    """Site of each near decision met: d n + c for the face of direction d
+    below cell c (n cells, flat [nz][ny][nx] index), 3 n + c for the edges of
+    cell c formed by the edge solve."""
+    n = ppm_flips()
+    out = np.zeros(max(n, 1), dtype=np.int64)
+    m = lib().orc_ppm_sites(out.ctypes.data_as(C.POINTER(C.c_long)), n)
+    return out[:m]
+
+
+def set_ppm_pick(sites, ordinals, nsite: int) -> None:
+    """With a band set (set_ppm_flip): take the other way, at each of ``sites``,
+    only its ``ordinals``-th near decision (counted among those met there; one
+    per site); sites below ``nsite``."""
+    s = np.ascontiguousarray(sites, dtype=np.int64)
+    o = np.ascontiguousarray(ordinals, dtype=np.int64)
+    lp = C.POINTER(C.c_long)
+    rc = lib().orc_set_ppm_pick(s.ctypes.data_as(lp), o.ctypes.data_as(lp), len(s), int(nsite))
+    if rc != 0:
+        raise ValueError(f"orc_set_ppm_pick: {rc}")

@@ -175,60 +175,204 @@ void orc_recon(int recon, double q0, double q1, double q2, double* lo, double* h
  *  C = 1.25. */
 static double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-static double ppm_interface(double am, double a0, double a1, double a2) {
-  const double C = 1.25;
-  double ai = (7.0 / 12.0) * (a0 + a1) - (1.0 / 12.0) * (am + a2);
-  if ((ai - a0) * (a1 - ai) < 0.0) {
-    double d2 = 3.0 * ((a0 - 2.0 * ai) + a1);
-    double d2l = (am - 2.0 * a0) + a1;
-    double d2r = (a0 - 2.0 * a1) + a2;
-    double lim = 0.0;
-    if (sgn(d2) == sgn(d2l) && sgn(d2) == sgn(d2r)) {
-      double m = C * fabs(d2l);
-      m = C * fabs(d2r) < m ? C * fabs(d2r) : m;
-      m = fabs(d2) < m ? fabs(d2) : m;
-      lim = sgn(d2) * m;
+/* Test hook (not part of the method): three PPM decisions make a face value
+ * jump when they change -- whether the interface value lies outside the
+ * interval of its two cells (step 2), whether the cell is at an extremum and
+ * whether D2 vanishes (step 3) -- so an evaluation in lower precision that
+ * rounds one of them the other way gives another, equally valid result.  With a
+ * band b > 0, a decision is "near" when a quantity it tests lies within b times
+ * the largest |a| of its stencil (12 times for D2) of the threshold and its two
+ * outcomes differ by more than that much; near decisions are counted in the
+ * order they are met and taken the other way: all of them (target -1), or only
+ * the target-th (a deterministic order needs one thread).  b = 0 (the default)
+ * is the method as written. */
+static double ppm_band = 0.0;
+static long ppm_target = -1;
+static long ppm_seen = 0;
+/* where each near decision was met: d n + c for the face of direction d below
+ * cell c (n cells), 3 n + c for the edges of cell c that the edge solve forms;
+ * and its ordinal among the near decisions met there */
+static long ppm_site = -1;
+static long* ppm_sites = NULL;
+static long ppm_cap = 0;
+static long ppm_site_prev = -1;
+static long ppm_local = 0;
+static int ppm_threads_before = 0;
+/* instead of a target: per site, the ordinal of the decision to take the other
+ * way there (-1: none) */
+static long* ppm_pick = NULL;
+static long ppm_npick = 0;
+
+static double amax(double a, double b) { return fabs(a) > fabs(b) ? fabs(a) : fabs(b); }
+
+static int ppm_near(double x, double scale) { return fabs(x) <= ppm_band * scale; }
+
+/* a near decision: counted, and whether to take it the other way */
+static int ppm_take(void) {
+  const long k = ppm_seen++;  /* the hook runs the oracle on one thread */
+  if (k >= ppm_cap) {
+    const long cap = ppm_cap ? 2 * ppm_cap : 4096;
+    long* n = (long*)realloc(ppm_sites, (size_t)cap * sizeof(long));
+    if (n) {
+      ppm_sites = n;
+      ppm_cap = cap;
     }
-    ai = 0.5 * (a0 + a1) - lim / 6.0;
   }
-  return ai;
+  if (k < ppm_cap) ppm_sites[k] = ppm_site;
+  if (ppm_site != ppm_site_prev) {
+    ppm_site_prev = ppm_site;
+    ppm_local = 0;
+  }
+  const long j = ppm_local++;
+  if (ppm_pick) return ppm_site >= 0 && ppm_site < ppm_npick && ppm_pick[ppm_site] == j;
+  return ppm_target < 0 || k == ppm_target;
+}
+
+/* step 2 for an interface value ai outside the interval of a0 and a1 */
+static double ppm_interface_clip(double am, double a0, double a1, double a2, double ai) {
+  const double C = 1.25;
+  double d2 = 3.0 * ((a0 - 2.0 * ai) + a1);
+  double d2l = (am - 2.0 * a0) + a1;
+  double d2r = (a0 - 2.0 * a1) + a2;
+  double lim = 0.0;
+  if (sgn(d2) == sgn(d2l) && sgn(d2) == sgn(d2r)) {
+    double m = C * fabs(d2l);
+    m = C * fabs(d2r) < m ? C * fabs(d2r) : m;
+    m = fabs(d2) < m ? fabs(d2) : m;
+    lim = sgn(d2) * m;
+  }
+  return 0.5 * (a0 + a1) - lim / 6.0;
+}
+
+static double ppm_interface(double am, double a0, double a1, double a2) {
+  double ai = (7.0 / 12.0) * (a0 + a1) - (1.0 / 12.0) * (am + a2);
+  int outside = (ai - a0) * (a1 - ai) < 0.0;
+  if (ppm_band > 0.0) {
+    const double sc = amax(amax(am, a0), amax(a1, a2));
+    if ((ppm_near(ai - a0, sc) || ppm_near(a1 - ai, sc)) &&
+        fabs(ppm_interface_clip(am, a0, a1, a2, ai) - ai) > ppm_band * sc && ppm_take())
+      outside = !outside;
+  }
+  return outside ? ppm_interface_clip(am, a0, a1, a2, ai) : ai;
+}
+
+/* step 3 at an extremum: the face values *am, *ap of cell a[2] scaled by
+ * D2lim / D2 (collapsed onto a_j where D2 = 0); the D2 = 0 test is a near
+ * decision only when may_flip is set (sc: the stencil scale) */
+static void ppm_extremum(const double* a, double* am, double* ap, double sc, int may_flip) {
+  const double C = 1.25;
+  const double aj = a[2];
+  double d2 = -2.0 * (6.0 * aj - 3.0 * (*am + *ap));
+  double d2c = (a[1] - 2.0 * aj) + a[3];
+  double d2l = (a[0] - 2.0 * a[1]) + aj;
+  double d2r = (aj - 2.0 * a[3]) + a[4];
+  double lim = 0.0;
+  if (sgn(d2) == sgn(d2c) && sgn(d2) == sgn(d2l) && sgn(d2) == sgn(d2r)) {
+    double m = C * fabs(d2l);
+    m = C * fabs(d2r) < m ? C * fabs(d2r) : m;
+    m = C * fabs(d2c) < m ? C * fabs(d2c) : m;
+    m = fabs(d2) < m ? fabs(d2) : m;
+    lim = sgn(d2) * m;
+  }
+  int nonzero = d2 != 0.0;
+  if (nonzero && may_flip && ppm_band > 0.0 && ppm_near(d2, 12.0 * sc)) {
+    const double r = lim / d2;
+    if (amax((*am - aj) * r, (*ap - aj) * r) > ppm_band * sc && ppm_take()) nonzero = 0;
+  }
+  if (nonzero) {
+    double r = lim / d2;
+    *am = aj + (*am - aj) * r;
+    *ap = aj + (*ap - aj) * r;
+  } else {
+    *am = aj;
+    *ap = aj;
+  }
+}
+
+/* step 3 elsewhere: the overshoot checks of Colella & Woodward */
+static void ppm_overshoot(double aj, double* am, double* ap) {
+  if (fabs(*ap - aj) >= 2.0 * fabs(*am - aj)) *ap = aj - 2.0 * (*am - aj);
+  if (fabs(*am - aj) >= 2.0 * fabs(*ap - aj)) *am = aj - 2.0 * (*ap - aj);
 }
 
 static void ppm_faces(const double* a, double* lo, double* hi) {
-  const double C = 1.25;
-  double aj = a[2];
+  const double aj = a[2];
   double am = ppm_interface(a[0], a[1], a[2], a[3]);
   double ap = ppm_interface(a[1], a[2], a[3], a[4]);
-  if ((ap - aj) * (aj - am) <= 0.0 || (a[3] - aj) * (aj - a[1]) <= 0.0) {
-    double d2 = -2.0 * (6.0 * aj - 3.0 * (am + ap));
-    double d2c = (a[1] - 2.0 * aj) + a[3];
-    double d2l = (a[0] - 2.0 * a[1]) + aj;
-    double d2r = (aj - 2.0 * a[3]) + a[4];
-    double lim = 0.0;
-    if (sgn(d2) == sgn(d2c) && sgn(d2) == sgn(d2l) && sgn(d2) == sgn(d2r)) {
-      double m = C * fabs(d2l);
-      m = C * fabs(d2r) < m ? C * fabs(d2r) : m;
-      m = C * fabs(d2c) < m ? C * fabs(d2c) : m;
-      m = fabs(d2) < m ? fabs(d2) : m;
-      lim = sgn(d2) * m;
+  int extremum = (ap - aj) * (aj - am) <= 0.0 || (a[3] - aj) * (aj - a[1]) <= 0.0;
+  double sc = 0.0;
+  if (ppm_band > 0.0) {
+    sc = amax(amax(amax(a[0], a[1]), amax(a[2], a[3])), amax(amax(a[4], am), ap));
+    /* either product can change sign if one of its factors is near zero; the
+     * outcome can change if every product that decides it can */
+    const int n1 = ppm_near(ap - aj, sc) || ppm_near(aj - am, sc);
+    /* two equal cell values are equal in any precision: an exact zero of
+     * a[3] - a_j or a_j - a[1] is not near */
+    const int n2 = (a[3] != aj && ppm_near(a[3] - aj, sc)) || (aj != a[1] && ppm_near(aj - a[1], sc));
+    const int p1 = (ap - aj) * (aj - am) > 0.0, p2 = (a[3] - aj) * (aj - a[1]) > 0.0;
+    if (extremum ? ((p1 || n1) && (p2 || n2)) : (n1 || n2)) {
+      double e_lo = am, e_hi = ap, o_lo = am, o_hi = ap;
+      ppm_extremum(a, &e_lo, &e_hi, sc, 0);
+      ppm_overshoot(aj, &o_lo, &o_hi);
+      if (amax(e_lo - o_lo, e_hi - o_hi) > ppm_band * sc && ppm_take()) extremum = !extremum;
     }
-    if (d2 != 0.0) {
-      double r = lim / d2;
-      am = aj + (am - aj) * r;
-      ap = aj + (ap - aj) * r;
-    } else {
-      am = aj;
-      ap = aj;
-    }
-  } else {
-    if (fabs(ap - aj) >= 2.0 * fabs(am - aj)) ap = aj - 2.0 * (am - aj);
-    if (fabs(am - aj) >= 2.0 * fabs(ap - aj)) am = aj - 2.0 * (ap - aj);
   }
+  if (extremum)
+    ppm_extremum(a, &am, &ap, sc, 1);
+  else
+    ppm_overshoot(aj, &am, &ap);
   *lo = am;
   *hi = ap;
 }
 
 void orc_ppm_faces(const double a[5], double* lo, double* hi) { ppm_faces(a, lo, hi); }
+
+void orc_set_ppm_flip(double band, long target) {
+  /* the count, the order and the sites are those of one thread */
+  if (band > 0.0 && ppm_band == 0.0) {
+    ppm_threads_before = omp_get_max_threads();
+    omp_set_num_threads(1);
+  } else if (!(band > 0.0) && ppm_band > 0.0 && ppm_threads_before > 0) {
+    omp_set_num_threads(ppm_threads_before);
+  }
+  ppm_band = band > 0.0 ? band : 0.0;
+  ppm_target = target < 0 ? -1 : target;
+  ppm_seen = 0;
+  ppm_site = -1;
+  ppm_site_prev = -1;
+  free(ppm_pick);
+  ppm_pick = NULL;
+  ppm_npick = 0;
+}
+
+int orc_set_ppm_pick(const long* site, const long* ordinal, long n, long nsite) {
+  long* p = (long*)malloc((size_t)(nsite > 0 ? nsite : 1) * sizeof(long));
+  if (!p) return ORC_ERR_NOMEM;
+  for (long q = 0; q < nsite; ++q) p[q] = -1;
+  for (long q = 0; q < n; ++q) {
+    if (site[q] < 0 || site[q] >= nsite || ordinal[q] < 0) {
+      free(p);
+      return ORC_ERR_INVALID_ARG;
+    }
+    p[site[q]] = ordinal[q];
+  }
+  free(ppm_pick);
+  ppm_pick = p;
+  ppm_npick = nsite;
+  ppm_seen = 0;
+  ppm_site = -1;
+  ppm_site_prev = -1;
+  return ORC_OK;
+}
+
+long orc_ppm_flips(void) { return ppm_seen; }
+
+long orc_ppm_sites(long* out, long n) {
+  const long m = ppm_seen < ppm_cap ? ppm_seen : ppm_cap;
+  const long c = n < m ? n : m;
+  for (long k = 0; k < c; ++k) out[k] = ppm_sites[k];
+  return c;
+}
 
 /* Fast and slow magnetosonic speeds from a^2 = gamma p / rho, total and normal
  * Alfven speeds (standard ideal-MHD wave speeds). */
@@ -745,6 +889,7 @@ static void faces(const grid_t* g, const orc_state* s, work_t* w, int d) {
             c[q] = at(g, i, j, wrap(k - 3 + q, g->nz));
         }
         double wl[7], wr[7], fl[7], cmax;
+        if (ppm_band > 0.0) ppm_site = (long)d * g->n + c[3];
         for (int v = 0; v < 7; ++v) {
           const double* q = w->w[frame[d][v]];
           double a[6];
@@ -923,6 +1068,7 @@ static void emfs_uct(const grid_t* g, const orc_state* s, work_t* w) {
         int im = dn(i, g->nx);
         long c = at(g, i, j, k);
         double b[6], v[6], bl, br, vl, vr;
+        if (ppm_band > 0.0) ppm_site = 3 * g->n + c;
         /* E_z at (i-1/2, j-1/2, k): P = x, Q = y */
         {
           for (int q = 0; q < 6; ++q) {  /* y-faces (i-3 .. i+2, j-1/2) */

@@ -117,6 +117,24 @@ double orc_limo3_phi(double theta);
 void orc_recon(int recon, double q0, double q1, double q2, double* lo, double* hi);
 /* PPM face values (*lo, *hi) of cell a[2] from the five cells a[0..4]. */
 void orc_ppm_faces(const double a[5], double* lo, double* hi);
+/* Test hook for lower-precision comparisons: with band > 0, the PPM decisions
+ * whose outcome jumps (interface value outside its cells, extremum, D2 = 0)
+ * and whose test lies within band (relative to the stencil's largest |a|) of
+ * the threshold are counted in the order met and taken the other way -- all of
+ * them (target < 0) or only the target-th.  While band > 0 the oracle runs on
+ * one thread (the count is then deterministic); band 0 restores the method
+ * and the thread count.  Resets the count. */
+void orc_set_ppm_flip(double band, long target);
+/* near decisions met since the last orc_set_ppm_flip */
+long orc_ppm_flips(void);
+/* the site each of them was met at: d n + c for the face of direction d
+ * below cell c (n cells, index [nz][ny][nx]), 3 n + c for the edges of cell c
+ * formed by the edge solve; copies at most n, returns the number copied */
+long orc_ppm_sites(long* out, long n);
+/* With a band set: instead of a target, take the other way at each site[q]
+ * only its ordinal[q]-th near decision (counted from 0 among those met at that
+ * site; one per site), sites below nsite.  Cleared by orc_set_ppm_flip. */
+int orc_set_ppm_pick(const long* site, const long* ordinal, long n, long nsite);
 
 /* Fast magnetosonic speed of a state (rho, p, Bn, Bt1, Bt2). */
 double orc_fast_speed(double gamma, double rho, double p, double bn, double bt1, double bt2);

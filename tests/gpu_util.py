@@ -197,3 +197,147 @@ def check_fp32_cycles(box, p, ncycles, integrator="rk2", tol=1e-5, weights=None)
         assert abs(dt_new - want_dt) <= tol * want_dt, (dt_new, want_dt)
         x0, dt = y, dt_new
     return worst
+
+
+# ---- stage-wise FP32 validity for PPM (reading R21)
+#
+# Three PPM decisions make a face value jump when they change (an interface
+# value outside the interval of its two cells, a cell at an extremum, D2 = 0),
+# so where one of them sits within FP32 rounding of its threshold an FP32 stage
+# can take the other, equally valid outcome and move the cells next to that face
+# by far more than rounding.  The oracle's test hook (oracle.set_ppm_flip) finds
+# every such near decision of a stage (its test within PPM_BAND of the threshold,
+# relative to its stencil, and its two outcomes different) and takes any chosen
+# ones the other way.  A stage is valid when every cell that departs from the
+# oracle stage by more than `tol` (plus the E^c tie slack for face fields) is
+# matched, in all eight fields at once and to `tol`, by the oracle stage with
+# some subset of the near decisions around it taken the other way (their
+# changes add: each decision moves one face's states).  Decisions that move a
+# cell by less than 1e-3 tol are not enumerated but added to its allowance.
+
+PPM_BAND = 1e-6  # about 16 FP32 ulps of the stencil's largest value
+
+
+def _cheb(cells, cell, shape):
+    """Chebyshev distance on the periodic grid between flat cell indices."""
+    nz, ny, nx = shape
+    k, j, i = cells // (nx * ny), (cells // nx) % ny, cells % nx
+    kb, jb, ib = cell // (nx * ny), (cell // nx) % ny, cell % nx
+    dk = np.abs((k - kb + nz // 2) % nz - nz // 2)
+    dj = np.abs((j - jb + ny // 2) % ny - ny // 2)
+    di = np.abs((i - ib + nx // 2) % nx - nx // 2)
+    return np.maximum(np.maximum(dk, dj), di)
+
+
+def ppm_flip_check(p, x, dt, got, w=1.0, w0=0.0, base=None, tol=1e-5, band=PPM_BAND, slack=None,
+                   small=1e-3, maxk=14):
+    """Check one FP32 PPM stage output `got` of input `x` (see above); returns
+    counts: cells above tol, near decisions, candidates, oracle runs, cells no
+    subset explains, and the largest remaining error of an explained cell."""
+    import itertools
+    want = oracle_stage(p, x, dt, w, w0, base)
+    shape = got["rho"].shape
+    ncell = int(np.prod(shape))
+    # a decision at a face moves that face's flux: the two cells beside it, and
+    # through the edge EMFs the face fields one cell further
+    reach = 1 if p.riemann == O.HLLC else 2
+    scale = {}
+    for grp in GROUPS:
+        sc = max(max(float(np.max(np.abs(want[f]))) for f in grp), 1e-300)
+        for f in grp:
+            scale[f] = sc
+    den = {f: (np.abs(want[f]) if f in ("rho", "en") else np.full(shape, scale[f])) for f in FIELDS}
+    resid = {f: (got[f] - want[f]) / den[f] for f in FIELDS}
+    allow = {f: (slack[f] / scale[f] if slack is not None and f in slack else np.zeros(shape))
+             for f in FIELDS}
+    bad = np.zeros(shape, bool)
+    for f in FIELDS:
+        bad |= np.abs(resid[f]) > tol + allow[f]
+    bcell = np.flatnonzero(bad)
+    out = {"bad": int(len(bcell)), "near": 0, "candidates": 0, "runs": 0, "unexplained": 0,
+           "residual": 0.0}
+    if len(bcell) == 0:
+        return out
+    try:
+        O.set_ppm_flip(band, 1 << 60)  # count and locate, take none the other way
+        oracle_stage(p, x, dt, w, w0, base)
+        sites = O.ppm_sites()
+        out["near"] = int(len(sites))
+        start = np.r_[0, np.flatnonzero(np.diff(sites) != 0) + 1]
+        ords = np.arange(len(sites)) - np.repeat(start, np.diff(np.r_[start, len(sites)]))
+        cells = sites % ncell
+        near_bad = np.zeros(len(sites), bool)
+        for b in bcell:
+            near_bad |= _cheb(cells, b, shape) <= reach
+        cand = np.flatnonzero(near_bad)
+        out["candidates"] = int(len(cand))
+        # one oracle run per group of candidates more than 2 reach apart: no
+        # departing cell is within reach of two decisions of a group
+        groups = []
+        for c in cand:
+            for g in groups:
+                if np.all(_cheb(cells[g], cells[c], shape) > 2 * reach):
+                    g.append(c)
+                    break
+            else:
+                groups.append([c])
+        out["runs"] = len(groups)
+        delta = {n: [] for n in range(len(bcell))}
+        at = [np.unravel_index(b, shape) for b in bcell]
+        for g in groups:
+            g = np.array(g)
+            O.set_ppm_flip(band, 1 << 60)
+            O.set_ppm_pick(sites[g], ords[g], 4 * ncell)
+            alt = oracle_stage(p, x, dt, w, w0, base)
+            for n, b in enumerate(bcell):
+                if not np.any(_cheb(cells[g], b, shape) <= reach):
+                    continue
+                v = np.array([(alt[f][at[n]] - want[f][at[n]]) / den[f][at[n]] for f in FIELDS])
+                if np.any(v != 0):
+                    delta[n].append(v)
+    finally:
+        O.set_ppm_flip(0.0)
+    for n in range(len(bcell)):
+        r0 = np.array([resid[f][at[n]] for f in FIELDS])
+        al = np.array([allow[f][at[n]] for f in FIELDS])
+        big = [v for v in delta[n] if np.max(np.abs(v)) > small * tol]
+        for v in delta[n]:
+            if np.max(np.abs(v)) <= small * tol:
+                al = al + np.abs(v)
+        best = np.inf
+        if len(big) <= maxk:
+            V = np.array(big).reshape(len(big), len(FIELDS))
+            for r in range(len(big) + 1):
+                for S in itertools.combinations(range(len(big)), r):
+                    best = min(best, float(np.max(np.abs(r0 - V[list(S)].sum(axis=0)) - al)))
+        out["residual"] = max(out["residual"], best)
+        if not best <= tol:
+            out["unexplained"] += 1
+    return out
+
+
+def check_fp32_ppm_cycles(box, p, ncycles, integrator="rk3", tol=1e-5):
+    """check_fp32_cycles for PPM: every stage by ppm_flip_check (with the E^c
+    tie slack for face fields under E^c).  Returns the totals over all stages."""
+    ws = STAGE_WEIGHTS[integrator]
+    x0, _, dt, rc = box.get_state_numpy()
+    assert rc == 0
+    tot = {"bad": 0, "near": 0, "candidates": 0, "runs": 0, "unexplained": 0, "residual": 0.0}
+    for c in range(ncycles):
+        box.step(1)
+        mids = [box.get_stage_output(k) for k in range(1, len(ws))]
+        y, _, dt_new, rc = box.get_state_numpy()
+        assert rc == 0
+        ins, outs = [x0] + mids, mids + [y]
+        for k, (w, w0) in enumerate(ws):
+            slack = ec_field_slack(p, ins[k], dt, weight=w) if p.emf == O.EMF_EC and p.riemann != O.HLLC \
+                else None
+            r = ppm_flip_check(p, ins[k], dt, outs[k], w, w0, x0, tol=tol, slack=slack)
+            print(f"cycle {c} stage {k + 1}: {r}", flush=True)
+            assert r["unexplained"] == 0, (c, k + 1, r)
+            for key, v in r.items():
+                tot[key] = max(tot[key], v) if key == "residual" else tot[key] + v
+        want_dt = p.cfl / O.max_invdt(p, x0)
+        assert abs(dt_new - want_dt) <= tol * want_dt, (dt_new, want_dt)
+        x0, dt = y, dt_new
+    return tot
