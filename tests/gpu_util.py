@@ -229,12 +229,32 @@ def _cheb(cells, cell, shape):
     return np.maximum(np.maximum(dk, dj), di)
 
 
+def _subset_sums(V):
+    s = np.zeros((1, V.shape[1]))
+    for v in V:
+        s = np.concatenate([s, s + v])
+    return s
+
+
+def _best_subset(r0, V, al):
+    """min over subsets S of the rows of V of max_f |r0 - sum_S V| - al (all
+    2^K subsets: the sums of the two halves' subsets met pairwise, in chunks)."""
+    h = len(V) // 2
+    a, b = _subset_sums(V[:h]), _subset_sums(V[h:])
+    t = r0 - a
+    best = np.inf
+    for i in range(0, len(t), 256):
+        e = np.max(np.abs(t[i:i + 256, None, :] - b[None, :, :]) - al, axis=2)
+        best = min(best, float(e.min()))
+    return best
+
+
 def ppm_flip_check(p, x, dt, got, w=1.0, w0=0.0, base=None, tol=1e-5, band=PPM_BAND, slack=None,
-                   small=1e-3, maxk=14):
+                   small=1e-3, maxk=22):
     """Check one FP32 PPM stage output `got` of input `x` (see above); returns
     counts: cells above tol, near decisions, candidates, oracle runs, cells no
-    subset explains, and the largest remaining error of an explained cell."""
-    import itertools
+    subset explains (or with more than maxk decisions of consequence around
+    them), and the largest remaining error."""
     want = oracle_stage(p, x, dt, w, w0, base)
     shape = got["rho"].shape
     ncell = int(np.prod(shape))
@@ -255,7 +275,7 @@ def ppm_flip_check(p, x, dt, got, w=1.0, w0=0.0, base=None, tol=1e-5, band=PPM_B
         bad |= np.abs(resid[f]) > tol + allow[f]
     bcell = np.flatnonzero(bad)
     out = {"bad": int(len(bcell)), "near": 0, "candidates": 0, "runs": 0, "unexplained": 0,
-           "residual": 0.0}
+           "residual": 0.0, "most_decisions": 0}
     if len(bcell) == 0:
         return out
     try:
@@ -304,12 +324,9 @@ def ppm_flip_check(p, x, dt, got, w=1.0, w0=0.0, base=None, tol=1e-5, band=PPM_B
         for v in delta[n]:
             if np.max(np.abs(v)) <= small * tol:
                 al = al + np.abs(v)
-        best = np.inf
-        if len(big) <= maxk:
-            V = np.array(big).reshape(len(big), len(FIELDS))
-            for r in range(len(big) + 1):
-                for S in itertools.combinations(range(len(big)), r):
-                    best = min(best, float(np.max(np.abs(r0 - V[list(S)].sum(axis=0)) - al)))
+        out["most_decisions"] = max(out["most_decisions"], len(big))
+        best = _best_subset(r0, np.array(big).reshape(len(big), len(FIELDS)), al) \
+            if len(big) <= maxk else np.inf
         out["residual"] = max(out["residual"], best)
         if not best <= tol:
             out["unexplained"] += 1
@@ -322,7 +339,8 @@ def check_fp32_ppm_cycles(box, p, ncycles, integrator="rk3", tol=1e-5):
     ws = STAGE_WEIGHTS[integrator]
     x0, _, dt, rc = box.get_state_numpy()
     assert rc == 0
-    tot = {"bad": 0, "near": 0, "candidates": 0, "runs": 0, "unexplained": 0, "residual": 0.0}
+    tot = {"bad": 0, "near": 0, "candidates": 0, "runs": 0, "unexplained": 0, "residual": 0.0,
+           "most_decisions": 0}
     for c in range(ncycles):
         box.step(1)
         mids = [box.get_stage_output(k) for k in range(1, len(ws))]
@@ -336,7 +354,7 @@ def check_fp32_ppm_cycles(box, p, ncycles, integrator="rk3", tol=1e-5):
             print(f"cycle {c} stage {k + 1}: {r}", flush=True)
             assert r["unexplained"] == 0, (c, k + 1, r)
             for key, v in r.items():
-                tot[key] = max(tot[key], v) if key == "residual" else tot[key] + v
+                tot[key] = max(tot[key], v) if key in ("residual", "most_decisions") else tot[key] + v
         want_dt = p.cfl / O.max_invdt(p, x0)
         assert abs(dt_new - want_dt) <= tol * want_dt, (dt_new, want_dt)
         x0, dt = y, dt_new
