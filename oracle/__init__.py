@@ -80,6 +80,9 @@ def lib():
         L.orc_mass_flux.argtypes = [C.POINTER(_Params), C.POINTER(_State), dp, dp, dp]
         L.orc_ec_tie_spread.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.c_double, dp, dp,
                                         dp]
+        L.orc_ec_ties.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.c_double, C.c_long,
+                                  C.POINTER(C.c_long), C.POINTER(C.c_int), dp, dp, dp]
+        L.orc_ec_ties.restype = C.c_long
         L.orc_step_vp.argtypes = [C.POINTER(_Params), C.POINTER(_State), C.POINTER(_Vpot), dp, dp,
                                   C.c_int, C.c_double]
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
@@ -195,6 +198,28 @@ def ec_tie_spread(p: Params, s: dict, band: float):
     if rc != OK:
         raise RuntimeError(f"orc_ec_tie_spread failed: {rc}")
     return out
+
+
+def ec_ties(p: Params, s: dict, band: float):
+    """The E^c upwind switches of state s whose |mass flux| <= band (band < 0:
+    relative to the largest |mass flux|), as arrays: edge (e n + c; e 0 E_x, 1
+    E_y, 2 E_z; c the flat cell index), slot (0..3: dq1, dq3, dp1, dp3, entering
+    the corner EMF as -dq1, +dq3, -dp1, +dp3 times 1/4), flux, l (taken for a
+    positive flux), r (negative flux); a zero flux takes (l + r) / 2."""
+    L = lib()
+    ps, cs = p.c(), _cstate(p, s)
+    args = (C.byref(ps), C.byref(cs), float(band))
+    n = L.orc_ec_ties(*args, 0, None, None, None, None, None)
+    if n < 0:
+        raise RuntimeError(f"orc_ec_ties failed: {n}")
+    edge = np.zeros(max(n, 1), np.int64)
+    slot = np.zeros(max(n, 1), np.int32)
+    flux, l, r = (np.zeros(max(n, 1)) for _ in range(3))
+    m = L.orc_ec_ties(*args, n, edge.ctypes.data_as(C.POINTER(C.c_long)),
+                      slot.ctypes.data_as(C.POINTER(C.c_int)), _dptr(flux), _dptr(l), _dptr(r))
+    if m != n:
+        raise RuntimeError(f"orc_ec_ties: {m} != {n}")
+    return edge[:n], slot[:n], flux[:n], l[:n], r[:n]
 
 
 def step(p: Params, s: dict, t: float, dt_next: float, nsteps: int, t_stop: float = 0.0,

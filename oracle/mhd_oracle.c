@@ -1328,81 +1328,140 @@ int orc_mass_flux(const orc_params* p, const orc_state* s, double* fx, double* f
   return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
 }
 
-/* Test helper for reduced-precision comparisons (Sec. 2.4, E^c): the upwind
+/* Test helpers for reduced-precision comparisons (Sec. 2.4, E^c): the upwind
  * switch of the corner EMF takes one of two candidate derivatives by the sign of
  * a face mass flux, so where that flux is within rounding of zero either
- * candidate is a valid result.  For every edge this returns how far the corner
- * EMF can move if each switch whose |mass flux| <= band takes another side than
- * the sign gives: a quarter of the sum of |L - R| over those switches (the EMF is
- * a quarter of a sum of the four upwinded terms).  Arrays are indexed like the
- * edge EMFs: sx at (i, j-1/2, k-1/2), sy at (i-1/2, j, k-1/2), sz at
- * (i-1/2, j-1/2, k). */
-static double tie_term(double s, double band, double l, double r) {
-  return fabs(s) <= band ? fabs(l - r) : 0.0;
+ * candidate, or their mean (a flux of exactly zero), is a valid result. */
+
+/* the operands of the corner EMF of edge e (0: E_x at (i, j-1/2, k-1/2), 1: E_y
+ * at (i-1/2, j, k-1/2), 2: E_z at (i-1/2, j-1/2, k)) of cell (i, j, k), as the
+ * stage passes them: a1 a2 b1 b2 c00 c10 c01 c11 sq1 sq3 sp1 sp3 */
+static void edge_operands(const grid_t* g, const work_t* w, int i, int j, int k, int e, double o[12]) {
+  double* const* fx = w->f[0];
+  double* const* fy = w->f[1];
+  double* const* fz = w->f[2];
+  const int im = dn(i, g->nx), jm = dn(j, g->ny), km = dn(k, g->nz);
+  const long c = at(g, i, j, k);
+  if (e == 2) { /* E_z: P = x, Q = y */
+    long cjm = at(g, i, jm, k), cim = at(g, im, j, k), cimjm = at(g, im, jm, k);
+    double t[12] = {-fx[F_B1][c], -fx[F_B1][cjm], fy[F_B2][c], fy[F_B2][cim], w->er[2][cimjm],
+                    w->er[2][cjm], w->er[2][cim], w->er[2][c], fx[F_RHO][c], fx[F_RHO][cjm],
+                    fy[F_RHO][c], fy[F_RHO][cim]};
+    memcpy(o, t, sizeof(t));
+  } else if (e == 0) { /* E_x: P = y, Q = z */
+    long ckm = at(g, i, j, km), cjm = at(g, i, jm, k), cjmkm = at(g, i, jm, km);
+    double t[12] = {-fy[F_B1][c], -fy[F_B1][ckm], fz[F_B2][c], fz[F_B2][cjm], w->er[0][cjmkm],
+                    w->er[0][ckm], w->er[0][cjm], w->er[0][c], fy[F_RHO][c], fy[F_RHO][ckm],
+                    fz[F_RHO][c], fz[F_RHO][cjm]};
+    memcpy(o, t, sizeof(t));
+  } else { /* E_y: P = z, Q = x */
+    long cim = at(g, im, j, k), ckm = at(g, i, j, km), cimkm = at(g, im, j, km);
+    double t[12] = {-fz[F_B1][c], -fz[F_B1][cim], fx[F_B2][c], fx[F_B2][ckm], w->er[1][cimkm],
+                    w->er[1][cim], w->er[1][ckm], w->er[1][c], fz[F_RHO][c], fz[F_RHO][cim],
+                    fx[F_RHO][c], fx[F_RHO][ckm]};
+    memcpy(o, t, sizeof(t));
+  }
 }
 
-int orc_ec_tie_spread(const orc_params* p, const orc_state* s, double band, double* sx,
-                      double* sy, double* sz) {
+/* the four switches of an edge: mass flux and the candidates (l, r) it picks
+ * between, in the order dq1, dq3, dp1, dp3 of orc_corner_emf */
+static void edge_switches(const double o[12], double sw[4][3]) {
+  const double a1 = o[0], a2 = o[1], b1 = o[2], b2 = o[3];
+  const double c00 = o[4], c10 = o[5], c01 = o[6], c11 = o[7];
+  const double t[4][3] = {{o[8], c01 - b2, c11 - b1},
+                          {o[9], b2 - c00, b1 - c10},
+                          {o[10], c10 - a2, c11 - a1},
+                          {o[11], a2 - c00, a1 - c01}};
+  memcpy(sw, t, sizeof(t));
+}
+
+/* the stage's faces and EMF operands of state s; band < 0 becomes |band| times
+ * the largest |mass flux| */
+static int ec_prepare(const orc_params* p, const orc_state* s, double* band, grid_t* g, work_t* w,
+                      int* bad) {
   int rc = check_params(p);
   if (rc) return rc;
-  /* band < 0: relative, |band| times the largest |mass flux| of the state */
-  if (!s || !sx || !sy || !sz || !(band == band)) return ORC_ERR_INVALID_ARG;
-  grid_t g;
-  grid_init(&g, p);
-  work_t w;
-  if (work_alloc(&w, g.n)) return ORC_ERR_NOMEM;
-  int bad = prim_all(&g, s, &w);
-  for (int d = 0; d < 3; ++d) faces(&g, s, &w, d);
-  emfs(&g, &w); /* fills the cell reference EMFs */
-  double* const* fx = w.f[0];
-  double* const* fy = w.f[1];
-  double* const* fz = w.f[2];
-  double* out[3] = {sx, sy, sz};
-  if (band < 0.0) {
+  if (!s || !(*band == *band)) return ORC_ERR_INVALID_ARG;
+  grid_init(g, p);
+  if (work_alloc(w, g->n)) return ORC_ERR_NOMEM;
+  *bad = prim_all(g, s, w);
+  for (int d = 0; d < 3; ++d) faces(g, s, w, d);
+  emfs(g, w); /* fills the cell reference EMFs */
+  if (*band < 0.0) {
     double m = 0.0;
     for (int d = 0; d < 3; ++d)
-      for (long c = 0; c < g.n; ++c) {
-        double a = fabs(w.f[d][F_RHO][c]);
+      for (long c = 0; c < g->n; ++c) {
+        double a = fabs(w->f[d][F_RHO][c]);
         m = a > m ? a : m;
       }
-    band = -band * m;
+    *band = -*band * m;
   }
+  return ORC_OK;
+}
+
+/* For every edge: how far the corner EMF can move if each switch whose |mass
+ * flux| <= band takes another side than the sign gives: a quarter of the sum of
+ * |L - R| over those switches (the EMF is a quarter of a sum of the four
+ * upwinded terms).  Arrays are indexed like the edge EMFs: sx at
+ * (i, j-1/2, k-1/2), sy at (i-1/2, j, k-1/2), sz at (i-1/2, j-1/2, k). */
+int orc_ec_tie_spread(const orc_params* p, const orc_state* s, double band, double* sx,
+                      double* sy, double* sz) {
+  if (!sx || !sy || !sz) return ORC_ERR_INVALID_ARG;
+  grid_t g;
+  work_t w;
+  int bad = 0;
+  int rc = ec_prepare(p, s, &band, &g, &w, &bad);
+  if (rc) return rc;
+  double* out[3] = {sx, sy, sz};
 #pragma omp parallel for schedule(static)
-  for (int k = 0; k < g.nz; ++k) {
-    int km = dn(k, g.nz);
-    for (int j = 0; j < g.ny; ++j) {
-      int jm = dn(j, g.ny);
-      for (int i = 0; i < g.nx; ++i) {
-        int im = dn(i, g.nx);
-        long c = at(&g, i, j, k);
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i)
         for (int e = 0; e < 3; ++e) {
-          /* the same operands as the corner EMF of this edge (emfs above) */
-          double a1, a2, b1, b2, c00, c10, c01, c11, sq1, sq3, sp1, sp3;
-          if (e == 2) { /* E_z: P = x, Q = y */
-            long cjm = at(&g, i, jm, k), cim = at(&g, im, j, k), cimjm = at(&g, im, jm, k);
-            a1 = -fx[F_B1][c]; a2 = -fx[F_B1][cjm]; b1 = fy[F_B2][c]; b2 = fy[F_B2][cim];
-            c00 = w.er[2][cimjm]; c10 = w.er[2][cjm]; c01 = w.er[2][cim]; c11 = w.er[2][c];
-            sq1 = fx[F_RHO][c]; sq3 = fx[F_RHO][cjm]; sp1 = fy[F_RHO][c]; sp3 = fy[F_RHO][cim];
-          } else if (e == 0) { /* E_x: P = y, Q = z */
-            long ckm = at(&g, i, j, km), cjm = at(&g, i, jm, k), cjmkm = at(&g, i, jm, km);
-            a1 = -fy[F_B1][c]; a2 = -fy[F_B1][ckm]; b1 = fz[F_B2][c]; b2 = fz[F_B2][cjm];
-            c00 = w.er[0][cjmkm]; c10 = w.er[0][ckm]; c01 = w.er[0][cjm]; c11 = w.er[0][c];
-            sq1 = fy[F_RHO][c]; sq3 = fy[F_RHO][ckm]; sp1 = fz[F_RHO][c]; sp3 = fz[F_RHO][cjm];
-          } else { /* E_y: P = z, Q = x */
-            long cim = at(&g, im, j, k), ckm = at(&g, i, j, km), cimkm = at(&g, im, j, km);
-            a1 = -fz[F_B1][c]; a2 = -fz[F_B1][cim]; b1 = fx[F_B2][c]; b2 = fx[F_B2][ckm];
-            c00 = w.er[1][cimkm]; c10 = w.er[1][cim]; c01 = w.er[1][ckm]; c11 = w.er[1][c];
-            sq1 = fz[F_RHO][c]; sq3 = fz[F_RHO][cim]; sp1 = fx[F_RHO][c]; sp3 = fx[F_RHO][ckm];
-          }
-          double t = tie_term(sq1, band, c01 - b2, c11 - b1) + tie_term(sq3, band, b2 - c00, b1 - c10) +
-                     tie_term(sp1, band, c10 - a2, c11 - a1) + tie_term(sp3, band, a2 - c00, a1 - c01);
-          out[e][c] = 0.25 * t;
+          double o[12], sw[4][3], t = 0.0;
+          edge_operands(&g, &w, i, j, k, e, o);
+          edge_switches(o, sw);
+          for (int q = 0; q < 4; ++q)
+            if (fabs(sw[q][0]) <= band) t += fabs(sw[q][1] - sw[q][2]);
+          out[e][at(&g, i, j, k)] = 0.25 * t;
         }
-      }
-    }
-  }
   free(w.block);
   return bad ? ORC_ERR_NONPHYSICAL : ORC_OK;
+}
+
+/* The switches whose |mass flux| <= band, in edge order: edge[q] = e n + c (e
+ * as above, c the cell index, n cells), slot[q] = 0..3 (dq1, dq3, dp1, dp3),
+ * and the mass flux and the two candidates.  At most cap are written; returns
+ * their total number (or an error code below zero). */
+long orc_ec_ties(const orc_params* p, const orc_state* s, double band, long cap, long* edge,
+                 int* slot, double* flux, double* l, double* r) {
+  grid_t g;
+  work_t w;
+  int bad = 0;
+  int rc = ec_prepare(p, s, &band, &g, &w, &bad);
+  if (rc) return rc;
+  long n = 0;
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i)
+        for (int e = 0; e < 3; ++e) {
+          double o[12], sw[4][3];
+          edge_operands(&g, &w, i, j, k, e, o);
+          edge_switches(o, sw);
+          for (int q = 0; q < 4; ++q) {
+            if (!(fabs(sw[q][0]) <= band)) continue;
+            if (n < cap) {
+              edge[n] = (long)e * g.n + at(&g, i, j, k);
+              slot[n] = q;
+              flux[n] = sw[q][0];
+              l[n] = sw[q][1];
+              r[n] = sw[q][2];
+            }
+            ++n;
+          }
+        }
+  free(w.block);
+  return bad ? ORC_ERR_NONPHYSICAL : n;
 }
 
 /* step to take this cycle: the CFL step, clipped so as not to pass t_stop */

@@ -87,6 +87,16 @@ int orc_mass_flux(const orc_params* p, const orc_state* s, double* fx, double* f
  * negative band is relative: |band| times the largest |mass flux| of the state. */
 int orc_ec_tie_spread(const orc_params* p, const orc_state* s, double band, double* sx,
                       double* sy, double* sz);
+/* The E^c upwind switches whose |mass flux| <= band (band < 0: relative to the
+ * largest |mass flux| of s): edge[q] = e n + c (e: 0 E_x at (i, j-1/2, k-1/2),
+ * 1 E_y at (i-1/2, j, k-1/2), 2 E_z at (i-1/2, j-1/2, k); c the cell, n cells),
+ * slot[q] 0..3 for the derivative terms dq1, dq3, dp1, dp3 of the corner EMF
+ * (entering it as -dq1, +dq3, -dp1, +dp3, times 1/4), the flux and the two
+ * candidates l (flux > 0) and r (flux < 0); a flux of zero takes their mean.
+ * Writes at most cap entries and returns the total count, or an error code
+ * below zero. */
+long orc_ec_ties(const orc_params* p, const orc_state* s, double band, long cap, long* edge,
+                 int* slot, double* flux, double* l, double* r);
 
 /* Advance nsteps cycles in place.  *dt_next is the step to use for the first
  * cycle (pass <= 0 to compute it from the state); on return it holds the CFL

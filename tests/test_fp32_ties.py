@@ -122,3 +122,93 @@ def test_stage_check_accepts_rounding_and_rejects_planted_errors():
         assert_stage_valid(stage_errors(bad, want, slack))
     with pytest.raises(AssertionError):
         assert_stage_valid(stage_errors(oracle_stage(p, s, dt * (1 + 1e-2)), want, slack))
+
+
+def test_switch_changes_reproduce_e0():
+    """E^0 is E^c with every upwind switch at the mean of its two candidates.
+    The face-field changes gpu_util.ec_switch_changes derives for that choice
+    at every switch (listed by oracle.ec_ties with an unbounded band), added to
+    the E^c stage, give the oracle's E^0 stage to rounding, while the two
+    stages themselves differ by about 1e-2: the switch list, the slot signs, the
+    edge stencil and the Stokes coefficients are all as the stage applies them."""
+    import dataclasses
+
+    from gpu_util import ec_switch_changes, oracle_stage
+    n = 16
+    s = I.turbulence((n, n, n), seed=3, kpeak=2.0, mach=0.8, b0=(0.2, 0.1, -0.1))
+    l = s.pop("_l")
+    p = O.Params(n, n, n, *l)
+    dt = p.cfl / O.max_invdt(p, s)
+    for w in (1.0, 0.5):
+        ec = oracle_stage(p, s, dt, w, 1.0 - w, s)
+        e0 = oracle_stage(dataclasses.replace(p, emf=O.EMF_E0), s, dt, w, 1.0 - w, s)
+        ties = O.ec_ties(p, s, 1e300)
+        assert len(ties[0]) == 12 * n ** 3
+        acc = {f: ec[f].copy().ravel() for f in ("bx", "by", "bz")}
+        for per_alt in ec_switch_changes(p, ties, dt, w, alternatives="mean"):
+            for comp, c, v in per_alt[0]:
+                acc[comp][c] += v
+        for f in ("bx", "by", "bz"):
+            sc = float(np.max(np.abs(e0[f])))
+            assert np.max(np.abs(acc[f].reshape(e0[f].shape) - e0[f])) <= 1e-14 * sc
+            assert np.max(np.abs(ec[f] - e0[f])) >= 1e-3 * sc
+
+
+def _crossing_state(n=32):
+    """v_x crosses zero just off the x-faces 5 and 21, where v_y jumps from -0.4
+    to 0.4 (a shear layer); B_x varies along y only (divergence-free), so the
+    y-derivatives of E_z that the x-face switches pick between differ by about
+    0.8 dB_x/dy on the two sides, while pressure and the other field components
+    are uniform and the faces' mass flux stays within 1e-7 of zero."""
+    c = (np.arange(n) + 0.5) / n
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    vx = (0.5 * np.sin(2 * np.pi * (x - 5.0 / n)) + 1e-8) * (1.0 + 0.3 * np.sin(2 * np.pi * y))
+    vy = np.where((x > 5.0 / n) & (x < 21.0 / n), 0.4, -0.4)
+    bx = 0.3 + 0.2 * np.sin(2 * np.pi * y)
+    sh = (n, n, n)
+    return I.to_float32_exact(I.assemble(1.0, vx, vy, np.full(sh, 0.3), 0.6, bx,
+                                         np.full(sh, 0.2), np.full(sh, 0.1), 5.0 / 3.0))
+
+
+def test_exact_tie_check_explains_other_choices_and_rejects_the_rest():
+    """A stage result in which some switches at near-zero mass flux take another
+    candidate (rounded to FP32) passes the E^c check with every departing face
+    explained; the same result with a face moved by 1e-4 of max |B| away from any
+    tie, or with a tie face moved by a quarter of what the other candidate gives
+    (neither it nor the mean of the two), fails."""
+    from gpu_util import check_fp32_stage, ec_switch_changes, oracle_stage
+    n = 32
+    s = _crossing_state(n)
+    p = O.Params(n, n, n)
+    dt = p.cfl / O.max_invdt(p, s)
+    want = oracle_stage(p, s, dt)
+    ties = O.ec_ties(p, s, -1e-5)
+    assert 0 < len(ties[0]) < 12 * n ** 3 // 10
+    changes = ec_switch_changes(p, ties, dt)
+    bsc = max(float(np.max(np.abs(want[f]))) for f in ("bx", "by", "bz"))
+    # the switches whose other candidate moves a face by more than 1e-5
+    big = [q for q, per_alt in enumerate(changes) if max(abs(v) for _, _, v in per_alt[0]) > 3e-5 * bsc]
+    assert len(big) >= 4
+    got = {f: v.copy() for f, v in want.items()}
+    flat = {f: got[f].reshape(-1) for f in ("bx", "by", "bz")}
+    for q in big[::7][:6]:
+        for comp, c, v in changes[q][0]:
+            flat[comp][c] += v
+    got = I.to_float32_exact(got)
+    e = check_fp32_stage(p, s, dt, got)
+    assert e["b_bad"] > 0 and e["b_unexplained"] == 0, e
+    # a departure where no switch reaches
+    tie_cells = {c for per_alt in changes for ch in per_alt for _, c, _ in ch}
+    far = next(c for c in range(n ** 3) if c not in tie_cells)
+    bad = {f: v.copy() for f, v in got.items()}
+    bad["by"].reshape(-1)[far] += 1e-4 * bsc
+    with pytest.raises(AssertionError):
+        check_fp32_stage(p, s, dt, bad)
+    # a tie face moved by a quarter of what the other candidate gives (the mean
+    # of the two gives half)
+    comp, c, v = max((ch for q in big for ch in changes[q][0]), key=lambda ch: abs(ch[2]))
+    assert abs(v) > 1e-4 * bsc
+    part = {f: v2.copy() for f, v2 in want.items()}
+    part[comp].reshape(-1)[c] += 0.25 * v
+    with pytest.raises(AssertionError):
+        check_fp32_stage(p, s, dt, I.to_float32_exact(part))
