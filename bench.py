@@ -309,7 +309,8 @@ def batched_c3(nbox: int = 64, steps: int = 20):
         bx.set_state(b["state"])
     batch = BoxBatch(boxes)
     batch.step(1)  # warm the kernels
-    # one launch shape for the whole batch, timed now (not from a cache)
+    # launch shapes for the batch (a common tile and cap, refined per box-shape
+    # class), timed now (not from a cache)
     tuner = Tuner(os.path.join(tempfile.gettempdir(), f"mhd_tune_{os.getpid()}.json"))
     choice = batch.tune(tuner, force=True)
     graph = batch.capture(steps)
@@ -353,6 +354,7 @@ def batched_c3(nbox: int = 64, steps: int = 20):
             "status_ok": all(rc == 0 for rc in rcs),
             "launch_shape": {"tile": TILE_NAMES.get(choice["tile"], str(choice["tile"])),
                              "zchunk_cap": choice["zchunk_cap"],
+                             "zchunk_by_nz": choice.get("zchunk_by_nz"),
                              "stage_ms_tuned": round(choice["best_ms"], 4),
                              "stage_ms_default": round(choice["default_ms"], 4),
                              "candidates": choice["candidates"]}}

@@ -224,8 +224,12 @@ typedef struct {
 /* Autotuner: time the first-stage launch of the whole group (one batched launch,
  * as mhd_step_batch issues it) for every tile and every z-chunk cap in
  * {automatic, 8, 16, 32, 64, 128}, reps >= 1 times each after one warm-up, on
- * stream (NULL: the stream of ctxs[0]); then give every context the fastest
- * shape (tile, min(cap, nz)).  The first-stage launch reads the current state
+ * stream (NULL: the stream of ctxs[0]), and take the fastest common shape
+ * (tile, min(cap, nz)); then refine per shape class: the contexts sharing nz,
+ * class by class (most cells first), try every other cap with the rest fixed
+ * and keep one that makes the group's launch more than 1 % faster.  Every
+ * context is left in its chosen shape (mhd_get_launch reads it; out->zchunk_cap
+ * is the common cap, out->best_ms the final time).  The first-stage launch reads the current state
  * and writes only the second buffer and the CFL maximum of the cycle being
  * prepared, so the state, t and the next step are unchanged.  Contexts must
  * share device, precision, solver, integrator and tile (as mhd_step_batch).

@@ -1,8 +1,9 @@
 """Launch-shape autotuner with a persistent cache.
 
 ``mhd_tune`` (libmhd) times the first-stage launch of a group of boxes, as one
-batched launch, for every stage-kernel tile and z-chunk cap, and gives every
-box the fastest shape.  This module keys that choice by the GPU, the precision,
+batched launch, for every stage-kernel tile and z-chunk cap, takes the fastest
+common shape and then refines the z-chunk per shape class (boxes sharing nz).
+This module keys that choice by the GPU, the precision,
 the scheme (solver, reconstruction, EMF) and the multiset of box shapes, keeps
 it in a JSON file, and applies a cached choice on later calls without timing
 anything.  The launch shape only
@@ -80,8 +81,9 @@ class Tuner:
         return self._cache.get(self.key(boxes))
 
     def apply(self, boxes, choice: dict):
+        per_nz = choice.get("zchunk_by_nz", {})
         for b in boxes:
-            b.set_launch(choice["tile"], choice["zchunk_cap"])
+            b.set_launch(choice["tile"], per_nz.get(str(b.shape[0]), choice["zchunk_cap"]))
 
     def measure(self, boxes, stream=None) -> dict:
         """Time every candidate on the GPU (mhd_tune) and apply the fastest."""
@@ -91,8 +93,11 @@ class Tuner:
         st = stream if stream is not None else boxes[0].stream
         L.check(lib.mhd_tune(arr, len(boxes), self.reps, C.c_void_p(st.cuda_stream), C.byref(res)),
                 "mhd_tune")
+        # the z-planes per work-group each shape class ended with
+        per_nz = {str(b.shape[0]): b.get_launch()[1] for b in boxes}
         return {"tile": res.tile, "zchunk_cap": res.zchunk_cap, "best_ms": res.best_ms,
-                "default_ms": res.default_ms, "candidates": res.candidates}
+                "default_ms": res.default_ms, "candidates": res.candidates,
+                "zchunk_by_nz": per_nz}
 
     def tune(self, boxes, stream=None, force: bool = False) -> dict:
         """Apply the cached shape for this group, or measure, store and apply."""

@@ -810,6 +810,27 @@ int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_resul
   const int def_tile = default_tile(ctxs[0]->p.precision);
   float best = 1e30f, def_ms = -1.0f;
   int best_tile = def_tile, best_cap = 0, tried = 0;
+  // median first-stage time of the whole group in its current shapes (the
+  // first launch warms up)
+  auto time_group = [&](float* med) -> int {
+    for (int r = 0; r <= reps; ++r) {
+      if (hipEventRecord(e0, st) != hipSuccess || launch_stage(ctxs, src, n, 0, 1.0, 0.0, st) != hipSuccess ||
+          hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return MHD_ERR_HIP;
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return MHD_ERR_HIP;
+      if (r > 0) times[r - 1] = ms;
+    }
+    for (int a = 1; a < reps; ++a)  // insertion sort of a few values
+      for (int b = a; b > 0 && times[b] < times[b - 1]; --b) {
+        float t = times[b];
+        times[b] = times[b - 1];
+        times[b - 1] = t;
+      }
+    *med = times[reps / 2];
+    ++tried;
+    return MHD_OK;
+  };
   for (int ti = 0; ti < ntile && rc == MHD_OK; ++ti)
     for (int ci = 0; ci < ncap && rc == MHD_OK; ++ci) {
       const int cap = caps[ci];
@@ -823,26 +844,9 @@ int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_resul
       if (dup) continue;
       for (int i = 0; i < n && rc == MHD_OK; ++i) rc = apply_shape(ctxs[i], tiles[ti], cap);
       if (rc != MHD_OK) break;
-      // the first launch warms up; the median of the timed ones counts
-      for (int r = 0; r <= reps && rc == MHD_OK; ++r) {
-        if (hipEventRecord(e0, st) != hipSuccess || launch_stage(ctxs, src, n, 0, 1.0, 0.0, st) != hipSuccess ||
-            hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-          rc = MHD_ERR_HIP;
-          break;
-        }
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MHD_ERR_HIP;
-        if (r > 0) times[r - 1] = ms;
-      }
+      float med = 0.0f;
+      rc = time_group(&med);
       if (rc != MHD_OK) break;
-      for (int a = 1; a < reps; ++a)  // insertion sort of a few values
-        for (int b = a; b > 0 && times[b] < times[b - 1]; --b) {
-          float t = times[b];
-          times[b] = times[b - 1];
-          times[b - 1] = t;
-        }
-      const float med = times[reps / 2];
-      ++tried;
       if (tiles[ti] == def_tile && cap == 0) def_ms = med;
       if (med < best) {
         best = med;
@@ -850,10 +854,76 @@ int mhd_tune(mhd_ctx* const* ctxs, int n, int reps, void* stream, mhd_tune_resul
         best_cap = cap;
       }
     }
+  // per shape class: boxes sharing nz share a z-chunk.  From the best common
+  // shape, each class in turn (most cells first) tries every other cap with
+  // the rest fixed and keeps one that makes the group's launch more than 1 %
+  // faster.
+  int* cls_cap = (int*)malloc(sizeof(int) * n);  // per box: the cap of its class
+  if (!cls_cap) rc = MHD_ERR_INVALID_ARG;
+  if (rc == MHD_OK) {
+    for (int i = 0; i < n && rc == MHD_OK; ++i) {
+      cls_cap[i] = best_cap;
+      rc = apply_shape(ctxs[i], best_tile, best_cap);
+    }
+  }
+  if (rc == MHD_OK && n > 1) {
+    float cur = 0.0f;
+    rc = time_group(&cur);
+    // classes in order of total cells, largest first
+    int* order = (int*)malloc(sizeof(int) * n);  // one representative box per class
+    long long* cells = (long long*)malloc(sizeof(long long) * n);
+    int ncls = 0;
+    if (!order || !cells) rc = MHD_ERR_INVALID_ARG;
+    for (int i = 0; i < n && rc == MHD_OK; ++i) {
+      int k = 0;
+      while (k < ncls && ctxs[order[k]]->p.nz != ctxs[i]->p.nz) ++k;
+      if (k == ncls) {
+        order[ncls] = i;
+        cells[ncls++] = 0;
+      }
+      cells[k] += ctxs[i]->ncell;
+    }
+    for (int a = 1; a < ncls; ++a)
+      for (int b = a; b > 0 && cells[b] > cells[b - 1]; --b) {
+        long long tc = cells[b];
+        cells[b] = cells[b - 1];
+        cells[b - 1] = tc;
+        int to = order[b];
+        order[b] = order[b - 1];
+        order[b - 1] = to;
+      }
+    for (int k = 0; k < ncls && rc == MHD_OK; ++k) {
+      const int nzk = ctxs[order[k]]->p.nz;
+      const int keep = cls_cap[order[k]];
+      int chosen = keep;
+      for (int ci = 0; ci < ncap && rc == MHD_OK; ++ci) {
+        const int cap = caps[ci];
+        // caps at or above nz all mean nz: try the first such once
+        if (cap == keep || (cap > 0 && ci > 0 && caps[ci - 1] >= nzk)) continue;
+        for (int i = 0; i < n && rc == MHD_OK; ++i)
+          if (ctxs[i]->p.nz == nzk) rc = apply_shape(ctxs[i], best_tile, cap);
+        float med = 0.0f;
+        if (rc == MHD_OK) rc = time_group(&med);
+        if (rc == MHD_OK && med < 0.99f * cur) {
+          cur = med;
+          chosen = cap;
+        }
+      }
+      for (int i = 0; i < n && rc == MHD_OK; ++i)
+        if (ctxs[i]->p.nz == nzk) {
+          cls_cap[i] = chosen;
+          rc = apply_shape(ctxs[i], best_tile, chosen);
+        }
+    }
+    if (rc == MHD_OK) best = cur < best ? cur : best;
+    free(order);
+    free(cells);
+  }
   // the timed launches wrote the second buffer
   for (int i = 0; i < n; ++i) ctxs[i]->stages_valid = 0;
   if (rc == MHD_OK)
-    for (int i = 0; i < n && rc == MHD_OK; ++i) rc = apply_shape(ctxs[i], best_tile, best_cap);
+    for (int i = 0; i < n && rc == MHD_OK; ++i) rc = apply_shape(ctxs[i], best_tile, cls_cap[i]);
+  free(cls_cap);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   free(src);

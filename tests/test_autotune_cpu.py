@@ -73,3 +73,21 @@ def test_corrupt_cache_is_ignored(tmp_path, monkeypatch, content):
     c = tuner.tune([FakeBox(64, 64, 64)])
     assert not c["cached"] and len(calls) == 1
     assert json.load(open(tmp_path / "tune.json"))
+
+
+def test_cached_per_class_zchunks_are_applied(tmp_path, monkeypatch):
+    """A cached choice with per-class z-chunks (boxes sharing nz) gives each box
+    its class's value, and the common cap to a class the entry does not name."""
+    res = {"tile": L.TILE_24x8, "zchunk_cap": 16, "best_ms": 1.0, "default_ms": 1.2,
+           "candidates": 20, "zchunk_by_nz": {"64": 32, "16": 16}}
+    tuner, calls = fake_tuner(tmp_path, monkeypatch, res)
+    boxes = [FakeBox(16, 16, 16), FakeBox(40, 24, 64), FakeBox(8, 8, 64)]
+    tuner.tune(boxes)
+    tuner2 = Tuner(str(tmp_path / "tune.json"))
+    boxes2 = [FakeBox(8, 8, 64), FakeBox(16, 16, 16), FakeBox(40, 24, 64)]
+    c = tuner2.tune(boxes2)
+    assert c["cached"] and len(calls) == 1
+    assert [b.launch for b in boxes2] == [(L.TILE_24x8, 32), (L.TILE_24x8, 16), (L.TILE_24x8, 32)]
+    other = FakeBox(8, 8, 48)
+    tuner2.apply([other], c)
+    assert other.launch == (L.TILE_24x8, 16)
