@@ -62,3 +62,26 @@ def test_served_results_match_oracle_and_alone_runs(precision):
     print(f"served {precision}: worst stage error vs the oracle {worst:.3e}")
     # requests draw different initial data (seeded translations)
     assert len({I.request_variant(r.seed) for r in reqs}) >= 8
+
+
+def test_served_at_the_stream_edges_fp64_bit_exact():
+    """The serving stream's own box edges (32 to 192): a short replay of 8
+    requests drawn like the benchmark's (edge uniform over the six edges,
+    seeded inits, a few steps each), FP64; every served result equals the oracle
+    on that request's input bit for bit, and its t."""
+    need_gpu()
+    from paper_2304_13746_amd.serve import EDGES, GpuBackend, Server, poisson_requests
+    reqs = poisson_requests(8, rate=200.0, seed=2311, edges=EDGES, steps=(2, 4))
+    assert max(r.edge for r in reqs) >= 128
+    be = GpuBackend(precision="fp64")
+    st = Server(be, budget_bytes=16 << 30, epoch_steps=2).run(reqs, keep_results=True)
+    assert len(st.done) == 8 and not st.rejected and all(d.status == 0 for d in st.done)
+    by_id = {r.rid: r for r in reqs}
+    for d in st.done:
+        r = by_id[d.rid]
+        print(f"request {r.rid}: edge {r.edge} init {r.init} steps {r.steps}", flush=True)
+        state, t, _ = d.result
+        o = O.copy_state(I.serving_state(r.edge, r.init, r.seed))
+        to, _, _ = O.step(O.Params(r.edge, r.edge, r.edge), o, 0.0, 0.0, r.steps)
+        g = {f: state[f].cpu().numpy() for f in FIELDS}
+        assert bit_equal(g, o) and t == to, r.rid
