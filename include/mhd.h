@@ -10,7 +10,7 @@
  *   PPM (Sec. 2.3),
  *   an HLLD or HLL Riemann solve on every x, y and z face (Sec. 2.3), corner EMFs
  *   by the upwind-by-contact E^c scheme, its E^0 and arithmetic variants, or
- *   the UCT-HLL edge solve (Sec. 2.4), the flux-divergence update of U
+ *   the UCT-HLL or UCT-HLLD edge solves (Sec. 2.4), the flux-divergence update of U
  *   and the constrained-transport update of face B (eq. ind_short); stages combined
  *   as U_s = w_s U* + w0_s U_0 (Sec. 2.7, Tab. weights); time step from eq. (cfl).
  * Energy is E = p/(gamma-1) + rho v^2/2 + B^2/2, dimensionless units without 4 pi.
