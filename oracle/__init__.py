@@ -6,6 +6,9 @@ Sec. 2.2-2.7).  Only the test suite, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import it; the GPU library never does, and
 the two share no code.
 
+``fp32_check`` (same package) compares a lower-precision stage result with the
+oracle's stage, allowing only the other valid choices at E^c upwind ties.
+
 States are dicts of eight float64 arrays shaped (nz, ny, nx): the cell-centred
 conserved variables ``rho, mx, my, mz, en`` and the face-centred field ``bx`` (at
 i-1/2), ``by`` (at j-1/2), ``bz`` (at k-1/2).
