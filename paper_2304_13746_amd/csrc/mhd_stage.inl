@@ -317,15 +317,19 @@ struct Tile {
 };
 
 // LDS layout (units of R): primitive plane, per-column exports, corner EMFs.
-template <typename R, int TX, int TY, int H>
+// The x- and y-face mass fluxes the E^c upwinding reads are xcons[0] and
+// ycons[0].  Where LDS allows, the corner EMFs are kept for two planes (NB = 2,
+// index: plane parity), so that publishing plane m's needs no barrier after the
+// reads of plane m-1's.
+template <typename R, int TX, int TY, int H, int NB = 1>
 struct Smem {
   using T = Tile<TX, TY, H>;
   R w[8][T::NW];
-  R xcons[5][T::NE], xez[T::NE], xmass[T::NE], xcmax[T::NE];
-  R ycons[5][T::NE], yez[T::NE], ymass[T::NE], ycmax[T::NE];
+  R xcons[5][T::NE], xez[T::NE], xcmax[T::NE];
+  R ycons[5][T::NE], yez[T::NE], ycmax[T::NE];
   R zex[T::NE], zey[T::NE], zmass[T::NE];
   R erz[T::NE], erx[T::NE], erxp[T::NE], ery[T::NE], eryp[T::NE];
-  R ez[T::NE], ex[T::NE], ey[T::NE];
+  R ez[NB][T::NE], ex[NB][T::NE], ey[NB][T::NE];
 };
 
 // Per-thread march values kept in LDS instead of registers: for FP64 with the
@@ -360,11 +364,19 @@ struct SmemPPM {
 };
 struct NoSmem {};
 
-template <typename R, int TX, int TY, bool HY, int H, bool DD = false>
+template <typename R, int TX, int TY, bool HY, int H, bool DD = false, int NB = 1>
 struct SmemAll {
-  std::conditional_t<HY, SmemHydro<R, TX, TY, H>, Smem<R, TX, TY, H>> s;
+  std::conditional_t<HY, SmemHydro<R, TX, TY, H>, Smem<R, TX, TY, H, NB>> s;
   Carry<R, TX, TY> c;
   std::conditional_t<DD, SmemPPM<R, TX, TY>, NoSmem> p;
+};
+
+// The layout a kernel instance uses: two corner-EMF planes unless that takes
+// the block past the 160 KiB of LDS a CU has (FP64 PPM on the 16x16 tile).
+template <typename R, int TX, int TY, bool HY, int H, bool DD>
+struct LdsLayout {
+  static constexpr int NB = sizeof(SmemAll<R, TX, TY, HY, H, DD, 2>) <= 160 * 1024 ? 2 : 1;
+  using type = SmemAll<R, TX, TY, HY, H, DD, NB>;
 };
 
 // Face-frame variable v of direction D (0: x, 1: y) of LDS cell iw, for a
@@ -449,7 +461,8 @@ stage_kernel(BatchArgs ba) {
   // limits them per face: the extra 15 KB of LDS would cost it a block per CU,
   // measured 20 % slower)
   constexpr bool DD = RECON == RECON_PPM && sizeof(R) == 8;
-  using SA_t = SmemAll<R, TX, TY, HY, H, DD>;
+  using SA_t = typename LdsLayout<R, TX, TY, HY, H, DD>::type;
+  constexpr int NB = LdsLayout<R, TX, TY, HY, H, DD>::NB;
   SA_t& SA = *reinterpret_cast<SA_t*>(smem_raw);
   auto& S = SA.s;
   constexpr bool CL = Carry<R, TX, TY>::in_lds;
@@ -600,6 +613,8 @@ stage_kernel(BatchArgs ba) {
 
   for (int m = z0 - 1; m <= z1; ++m) {
     const int km = wrapi(m, a.nz);
+    // corner-EMF buffers of planes m and m-1
+    const int pm = NB == 2 ? (m & 1) : 0, pm1 = NB == 2 ? (pm ^ 1) : 0;
     // FP32: the next plane's state (and halo item) is loaded before the face
     // solves, so its memory latency overlaps them (src is never written by this
     // launch); FP64 and FP32 PPM have no registers to spare for it (measured:
@@ -723,12 +738,11 @@ stage_kernel(BatchArgs ba) {
       } else if (corner_x) {
         const int ec = T::e(TX, -1);
         S.xez[ec] = -fx.fb1;
-        S.xmass[ec] = fx.cons[0];
+        S.xcons[0][ec] = fx.cons[0];
       } else {
 #pragma unroll
         for (int q = 0; q < 5; ++q) S.xcons[q][ex_me] = fx.cons[q];
         S.xez[ex_me] = -fx.fb1;
-        S.xmass[ex_me] = fx.cons[0];
         S.xcmax[ex_me] = fx.cmax;
       }
     }
@@ -775,12 +789,11 @@ stage_kernel(BatchArgs ba) {
       } else if (corner_y) {
         const int ec = T::e(-1, TY);
         S.yez[ec] = fy.fb2;
-        S.ymass[ec] = fy.cons[0];
+        S.ycons[0][ec] = fy.cons[0];
       } else {
 #pragma unroll
         for (int q = 0; q < 5; ++q) S.ycons[q][ex_me] = fy.cons[q];
         S.yez[ex_me] = fy.fb2;
-        S.ymass[ex_me] = fy.cons[0];
         S.ycmax[ex_me] = fy.cmax;
       }
     }
@@ -890,7 +903,9 @@ stage_kernel(BatchArgs ba) {
       const int jw = T::w(xci, xcj);
       put_cell<HY>(S, jw, wx);
     }
-    __syncthreads();
+    // (nothing below reads the plane before the next iteration, and a barrier
+    // comes first: after C without corner EMFs or with one EMF plane, after D
+    // with them)
 
     // ---------------- C: corner EMFs, cell update of plane m-1
     R ez_new = 0, ex_new = 0, ey_new = 0;
@@ -898,8 +913,8 @@ stage_kernel(BatchArgs ba) {
     if (do_ez && m >= z0 && m < z1) {
       const int e_s = T::e(ci, cj - 1), e_w = T::e(ci - 1, cj), e_sw = T::e(ci - 1, cj - 1);
       ez_new = corner_emf<EMF>(S.xez[ex_me], S.xez[e_s], S.yez[ex_me], S.yez[e_w], S.erz[e_sw],
-                          S.erz[e_s], S.erz[e_w], S.erz[ex_me], S.xmass[ex_me], S.xmass[e_s],
-                          S.ymass[ex_me], S.ymass[e_w]);
+                          S.erz[e_s], S.erz[e_w], S.erz[ex_me], S.xcons[0][ex_me], S.xcons[0][e_s],
+                          S.ycons[0][ex_me], S.ycons[0][e_w]);
     }
     if (m >= z0) {
       if (do_ex) {
@@ -954,8 +969,8 @@ stage_kernel(BatchArgs ba) {
           // the face field is updated after the edge solve
         } else if constexpr (CT == CT_FACE) {
           const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
-          R bxn = (gld(a.src[5], o) - tau_y * (S.ez[e_n] - S.ez[ex_me])) + tau_z * (ey_new - ey_prev);
-          R byn = (gld(a.src[6], o) - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[e_e] - S.ez[ex_me]);
+          R bxn = (gld(a.src[5], o) - tau_y * (S.ez[pm1][e_n] - S.ez[pm1][ex_me])) + tau_z * (ey_new - ey_prev);
+          R byn = (gld(a.src[6], o) - tau_z * (ex_new - ex_prev)) + tau_x * (S.ez[pm1][e_e] - S.ez[pm1][ex_me]);
           if constexpr (MODE == MODE_COMBINE) {
             bxn = a.w * bxn + a.w0 * gld<R>(a.dst[5], o + a.boff);
             byn = a.w * byn + a.w0 * gld<R>(a.dst[6], o + a.boff);
@@ -965,13 +980,17 @@ stage_kernel(BatchArgs ba) {
         }
       }
     }
-    __syncthreads();  // reads of corner-EMF buffers of plane m-1 done
+    // the partial update's reads of the face exports and C's reads of plane
+    // m-1's corner EMFs end before they are overwritten: without corner EMFs,
+    // or with one EMF plane, here; with two, the barrier after D does it (D
+    // writes the other plane's buffers than C read)
+    if constexpr (NE || NB == 1) __syncthreads();
 
     // ---------------- D: publish corner EMFs; E: B_z on face m-1/2
     if constexpr (!NE) {
-      if (do_ez) S.ez[ex_me] = ez_new;
-      if (do_ex) S.ex[ex_me] = ex_new;
-      if (do_ey) S.ey[ex_me] = ey_new;
+      if (do_ez) S.ez[pm][ex_me] = ez_new;
+      if (do_ex) S.ex[pm][ex_me] = ex_new;
+      if (do_ey) S.ey[pm][ex_me] = ey_new;
       __syncthreads();
     }
     if constexpr (MODE != MODE_MEASURE) {
@@ -983,7 +1002,7 @@ stage_kernel(BatchArgs ba) {
           // the face field is updated after the edge solve
         } else if constexpr (CT == CT_FACE) {
           const int e_e = T::e(ci + 1, cj), e_n = T::e(ci, cj + 1);
-          R bzn = (bz_m - tau_x * (S.ey[e_e] - ey_new)) + tau_y * (S.ex[e_n] - ex_new);
+          R bzn = (bz_m - tau_x * (S.ey[pm][e_e] - ey_new)) + tau_y * (S.ex[pm][e_n] - ex_new);
           if constexpr (MODE == MODE_COMBINE) bzn = a.w * bzn + a.w0 * gld<R>(a.dst[7], o + a.boff);
           gst(a.dst[7], o, bzn);
         } else {
@@ -1039,8 +1058,8 @@ template <typename R, int SOLVER, int RECON, int EMF, int CT, int MODE, int TX, 
 static hipError_t launch_one(const BatchArgs& ba, hipStream_t st, bool prepare) {
   using T = Tile<TX, TY>;
   const size_t lds =
-      sizeof(SmemAll<R, TX, TY, SOLVER == SOLVER_HLLC, RECON == RECON_PPM ? 3 : 2,
-                     RECON == RECON_PPM && sizeof(R) == 8>);
+      sizeof(typename LdsLayout<R, TX, TY, SOLVER == SOLVER_HLLC, RECON == RECON_PPM ? 3 : 2,
+                                RECON == RECON_PPM && sizeof(R) == 8>::type);
   auto fn = stage_kernel<R, SOLVER, RECON, EMF, CT, MODE, TX, TY>;
   if (prepare)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
