@@ -283,3 +283,44 @@ def test_fp32_every_stage_valid(opts):
     worst = check_fp32_cycles(box, p, 5, integrator=opts.get("integrator", "rk2"))
     box.close()
     print("worst", worst)
+
+
+@pytest.mark.parametrize("b0", [(0.0, 0.0, 0.0), (0.0, 0.3, -0.2)])
+def test_hlld_degenerate_normal_field_fp64_bit_exact(b0):
+    """HLLD where its Alfven fans collapse (Sec. 2.3): with B = 0 everywhere the
+    outer star states and the double-star states coincide (no rotational
+    waves) and the field must stay exactly zero; with a mean field that has no
+    x-component, every x-face starts with B_n = 0 (the sign of B_n, which
+    picks the double-star coupling, is zero there).  Ragged box, supersonic
+    turbulence, 4 RK2 cycles: state and dt sequence bit-identical to the
+    oracle."""
+    need_gpu()
+    dims = (37, 29, 22)
+    s = I.turbulence(dims, seed=61, kpeak=2.0, mach=1.5, b0=b0)
+    l = s.pop("_l")
+    print("hlld degenerate", b0, dims, flush=True)
+    g, o, gd, od, (tg, to) = run_both(s, dims, 4, l=l, per_step=True, zchunk=5)
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+    if not any(b0):
+        for f in ("bx", "by", "bz"):
+            assert not g[f].any()
+
+
+def test_hlld_zero_field_fp32_within_tolerance():
+    """FP32 HLLD with B = 0 everywhere (every EMF exactly zero in both
+    precisions, so no E^c upwind choice can differ): within 1e-5 of the FP64
+    oracle run from the same FP32-rounded input after 4 cycles; the field
+    stays exactly zero."""
+    need_gpu()
+    dims = (40, 24, 32)
+    s = I.turbulence(dims, seed=67, kpeak=2.0, mach=1.0, b0=(0.0, 0.0, 0.0))
+    l = s.pop("_l")
+    s = I.to_float32_exact(s)
+    print("hlld zero field fp32", dims, flush=True)
+    g, o, _, _, _ = run_both(s, dims, 4, l=l, precision="fp32")
+    err = max_rel(g, o)
+    print("hlld zero field fp32 max rel", err)
+    assert err <= 1e-5
+    for f in ("bx", "by", "bz"):
+        assert not g[f].any()
