@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import FIELDS, bit_equal, max_rel, need_gpu, run_both
+from gpu_util import (FIELDS, bit_equal, check_fp32_cycles, gpu_box, max_rel, need_gpu,
+                      oracle_params, run_both)
 from paper_2304_13746_amd import _lib as L
 from paper_2304_13746_amd import inputs as I
 
@@ -324,3 +325,54 @@ def test_hlld_zero_field_fp32_within_tolerance():
     assert err <= 1e-5
     for f in ("bx", "by", "bz"):
         assert not g[f].any()
+
+
+@pytest.mark.parametrize("riemann,gamma,cfl", [("hlld", 1.4, 0.6), ("hll", 2.0, 0.15)])
+def test_other_gamma_and_cfl_fp64_bit_exact(riemann, gamma, cfl):
+    """The adiabatic index (energy closure, Sec. 2.1; wave speeds) and the CFL
+    number of eq. (cfl) are inputs of the step, not constants of the kernel:
+    with values other than the benchmark's 5/3 and 0.3, on a ragged box with
+    a field along all three axes, 3 RK2 cycles, state and dt sequence
+    bit-identical to the oracle run with the same gamma and CFL number."""
+    need_gpu()
+    dims = (29, 37, 22)
+    s = I.turbulence(dims, seed=71, kpeak=2.0, mach=1.0, b0=(0.15, -0.1, 0.2), gamma=gamma)
+    l = s.pop("_l")
+    print("gamma", gamma, "cfl", cfl, riemann, dims, flush=True)
+    box = gpu_box(dims, l, riemann=riemann, gamma=gamma, cfl=cfl, zchunk=5)
+    box.set_state(s, 0.0, 0.0)
+    p = oracle_params(dims, l, riemann, gamma=gamma, cfl=cfl)
+    o = O.copy_state(s)
+    t, dt = 0.0, 0.0
+    gd, od = [], []
+    for _ in range(3):
+        box.step(1)
+        _, _, dg, _ = box.get_state()
+        gd.append(dg)
+        t, dt, _ = O.step(p, o, t, dt, 1)
+        od.append(dt)
+    g, tg, _, rc = box.get_state_numpy()
+    box.close()
+    assert rc == 0
+    assert bit_equal(g, o)
+    assert gd == od and tg == t
+
+
+def test_other_gamma_fp32_stagewise():
+    """FP32 with gamma = 1.4 and CFL 0.5: every stage of 3 cycles against the
+    oracle's stage on the GPU's own input of that stage, with the same gamma
+    (fluid to 1e-5, face fields to 1e-5 up to E^c ties), and each step
+    against eq. (cfl) with the same CFL number."""
+    need_gpu()
+    dims = (32, 24, 20)
+    gamma, cfl = 1.4, 0.5
+    s = I.turbulence(dims, seed=73, kpeak=2.0, mach=1.0, b0=(0.2, 0.1, 0.0), gamma=gamma)
+    l = s.pop("_l")
+    s = I.to_float32_exact(s)
+    print("fp32 gamma", gamma, "cfl", cfl, dims, flush=True)
+    box = gpu_box(dims, l, precision="fp32", gamma=gamma, cfl=cfl)
+    box.set_state(s)
+    p = oracle_params(dims, l, gamma=gamma, cfl=cfl)
+    worst = check_fp32_cycles(box, p, 3)
+    box.close()
+    print("fp32 gamma 1.4: worst stage errors", worst)
