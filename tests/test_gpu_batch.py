@@ -135,3 +135,40 @@ def test_batch_of_mixed_physics_matches_oracle():
         t, dt, _ = O.step(p, o, 0.0, 0.0, n)
         assert rc == 0
         assert bit_equal(g, o) and tg == t and dg == dt, dims
+
+
+@pytest.mark.parametrize("riemann,recon,integrator", [("hlld", "ppm", "rk3"),
+                                                      ("hllc", "ppm", "rk2"),
+                                                      ("hllc", "limo3", "rk3")])
+def test_batch_of_option_builds_matches_oracle(riemann, recon, integrator):
+    """Batched launches of the option builds with their own LDS layouts and
+    halos: PPM (three-cell halo, five-plane z-window) with HLLD, and the
+    field-free HLLC build with PPM and with LimO3; three uneven boxes with
+    their own step counts, each bit-identical to the oracle run alone."""
+    torch = need_gpu()
+    import oracle as O
+    from gpu_util import oracle_params
+    from paper_2304_13746_amd.batch import BoxBatch
+    from paper_2304_13746_amd.box import MHDBox
+    b0 = (0.0, 0.0, 0.0) if riemann == "hllc" else (0.2, -0.1, 0.1)
+    cases = [((26, 19, 21), 3, 91), ((16, 40, 12), 2, 93), ((33, 24, 30), 3, 95)]
+    stream = torch.cuda.Stream()
+    boxes, states, lens = [], [], []
+    for dims, _, seed in cases:
+        s = I.turbulence(dims, seed=seed, kpeak=2.0, mach=1.2, b0=b0)
+        l = s.pop("_l")
+        bx = MHDBox(*dims, *l, riemann=riemann, recon=recon, integrator=integrator, stream=stream)
+        bx.set_state(s)
+        boxes.append(bx)
+        states.append(s)
+        lens.append(l)
+    print("option batch", riemann, recon, integrator, [c[0] for c in cases], flush=True)
+    BoxBatch(boxes).step([c[1] for c in cases])
+    for (dims, n, _), bx, s, l in zip(cases, boxes, states, lens):
+        g, tg, dg, rc = bx.get_state_numpy()
+        bx.close()
+        p = oracle_params(dims, l, riemann, integrator, recon=recon)
+        o = O.copy_state(s)
+        t, dt, _ = O.step(p, o, 0.0, 0.0, n)
+        assert rc == 0
+        assert bit_equal(g, o) and tg == t and dg == dt, dims
