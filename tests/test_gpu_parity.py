@@ -376,3 +376,43 @@ def test_other_gamma_fp32_stagewise():
     worst = check_fp32_cycles(box, p, 3)
     box.close()
     print("fp32 gamma 1.4: worst stage errors", worst)
+
+
+STRESS = {"low_beta": dict(p0=0.01, b0=(2.0, 1.0, 0.5), mach=1.0),
+          "high_mach": dict(p0=0.6, b0=(0.05, 0.0, 0.0), mach=3.0)}
+
+
+@pytest.mark.parametrize("riemann", ["hlld", "hll"])
+@pytest.mark.parametrize("regime", sorted(STRESS))
+def test_stress_regimes_fp64_bit_exact(regime, riemann):
+    """Away from the benchmark's moderate state: a field-dominated plasma
+    (pressure 0.01 against a field of magnitude 2.3, plasma beta about 4e-3,
+    where the pressure is a small difference of the energy and the magnetic
+    energy and the Alfven fans are wide) and supersonic turbulence at rms
+    Mach 3 in a weak field (strong compressions).  5 RK2 cycles on a ragged
+    box: state and dt sequence bit-identical to the oracle."""
+    need_gpu()
+    dims = (30, 22, 26)
+    s = I.turbulence(dims, seed=97, kpeak=2.0, **STRESS[regime])
+    l = s.pop("_l")
+    print("stress", regime, riemann, dims, flush=True)
+    g, o, gd, od, (tg, to) = run_both(s, dims, 5, l=l, riemann=riemann, per_step=True, zchunk=7)
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
+
+
+def test_low_beta_fp32_stagewise():
+    """FP32 in the field-dominated regime above: every stage of 3 cycles
+    against the oracle's stage on the GPU's own input (fluid to 1e-5, face
+    fields to 1e-5 up to E^c ties)."""
+    need_gpu()
+    dims = (30, 22, 26)
+    s = I.turbulence(dims, seed=97, kpeak=2.0, **STRESS["low_beta"])
+    l = s.pop("_l")
+    s = I.to_float32_exact(s)
+    print("low beta fp32", dims, flush=True)
+    box = gpu_box(dims, l, precision="fp32")
+    box.set_state(s)
+    worst = check_fp32_cycles(box, oracle_params(dims, l), 3)
+    box.close()
+    print("low beta fp32: worst stage errors", worst)
