@@ -416,3 +416,23 @@ def test_low_beta_fp32_stagewise():
     worst = check_fp32_cycles(box, oracle_params(dims, l), 3)
     box.close()
     print("low beta fp32: worst stage errors", worst)
+
+
+@pytest.mark.parametrize("regime,emf,recon", [("low_beta", "uct_hlld", "plm"),
+                                              ("low_beta", "uct_hll", "limo3"),
+                                              ("low_beta", "arith", "ppm"),
+                                              ("high_mach", "ec", "ppm"),
+                                              ("high_mach", "e0", "limo3")])
+def test_stress_regimes_options_fp64_bit_exact(regime, emf, recon):
+    """The two stress regimes with the other corner-EMF schemes (the edge
+    solves see the wide Alfven fans of the low-beta plasma) and the other
+    reconstructions (the limiters' switches under strong compressions): 3 RK2
+    cycles, state and dt sequence bit-identical to the oracle."""
+    need_gpu()
+    dims = (30, 22, 26)
+    s = I.turbulence(dims, seed=97, kpeak=2.0, **STRESS[regime])
+    l = s.pop("_l")
+    print("stress options", regime, emf, recon, dims, flush=True)
+    g, o, gd, od, (tg, to) = run_both(s, dims, 3, l=l, per_step=True, emf=emf, recon=recon)
+    assert bit_equal(g, o)
+    assert gd == od and tg == to
